@@ -1,0 +1,221 @@
+/*
+ * abx.h -- C-ABI of libabx, a linear-BVH geometric search library for the
+ * AMD MI355X (gfx950).
+ *
+ * The method is the one of ArborX (Lebrun-Grandie, Prokopenko, Turcksin,
+ * Slattery; arXiv:1908.11807):
+ *   - construction (section 2.1): boxes of the primitives, scene box, Morton
+ *     codes, sort, Karras hierarchy, bottom-up internal boxes;
+ *   - traversal (section 2.2): spatial queries by an iterative stack
+ *     traversal with count-then-fill (2P) output, nearest queries by a stack
+ *     traversal that visits the nearer child first and stops when no
+ *     remaining candidate can improve, query ordering by Morton code;
+ *   - interface (section 2.3): build from primitives, query with a batch of
+ *     predicates, results as CSR offsets + indices.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers are DEVICE pointers unless the parameter is marked (host).
+ *   - The library never allocates or frees device memory.  Every device
+ *     buffer is owned by the caller; its size comes from the matching
+ *     *_sizes call.  Scratch buffers may be reused between calls once the
+ *     stream has passed the call that used them.
+ *   - Every call enqueues its kernels on `stream` (0 = the null stream) and
+ *     returns after enqueueing, except where a host read is stated.
+ *   - Arguments are validated before anything is launched; errors are
+ *     return codes, never exceptions.  On ABX_ERR_HIP the failing HIP error
+ *     code is available from abx_last_hip_error() (per host thread).
+ *   - Indices are int32, 0-based positions in the caller's primitive array.
+ *     n, m and every result count must be below 2^31 (ABX_ERR_OVERFLOW).
+ *   - Primitive and query coordinates are float32, row-major.
+ *   - A handle (abx_bvh) lives in host memory and points into the caller's
+ *     tree buffer; it is immutable after a successful build and may be
+ *     queried concurrently from several streams, one scratch buffer per
+ *     in-flight call.
+ */
+#ifndef ABX_H
+#define ABX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *abx_stream_t; /* a hipStream_t */
+
+typedef enum {
+  ABX_OK = 0,
+  ABX_ERR_INVALID_ARG = 1,   /* bad pointer, size, kind or option          */
+  ABX_ERR_INVALID_INPUT = 2, /* a primitive coordinate is NaN or infinite  */
+  ABX_ERR_CAPACITY = 3,      /* result buffer too small; see query_spatial */
+  ABX_ERR_OVERFLOW = 4,      /* a size or result count reaches 2^31        */
+  ABX_ERR_HIP = 5,           /* a HIP runtime call failed                  */
+  ABX_ERR_UNSUPPORTED = 6    /* valid request this build does not handle   */
+} abx_status;
+
+/* Primitives (section 2.1 "Construct AABBs": a point is a degenerate box). */
+typedef enum {
+  ABX_PRIM_POINTS = 0, /* float32 [n,3]: x y z                      */
+  ABX_PRIM_BOXES = 1   /* float32 [n,6]: lo x y z, hi x y z (lo<=hi) */
+} abx_prim_kind;
+
+/* Storage of the internal nodes.
+ *   FP32: 64 B per internal node -- both children's float32 boxes and
+ *         their references; leaves store only the permutation index.
+ *   Q16 : 32 B per internal node -- children's boxes quantised to 16 bits
+ *         per coordinate on the scene box's grid, rounded outward so every
+ *         quantised box contains the exact one; leaves keep the exact
+ *         float32 primitive box, so results are identical to FP32.  (The
+ *         paper names quantised bounds as a way to cut BVH bandwidth,
+ *         section 2 literature review.) */
+typedef enum { ABX_NODES_FP32 = 0, ABX_NODES_Q16 = 1 } abx_node_format;
+
+typedef struct {
+  abx_prim_kind kind;
+  const float *data; /* device, [n,3] or [n,6] */
+  int64_t n;
+} abx_primitives;
+
+typedef struct {
+  abx_node_format node_format;
+  int32_t morton_bits; /* bits per axis of the Morton code: 10 (30-bit codes)
+                          or 21 (63-bit codes, the default when 0) */
+} abx_build_options;
+
+/* Spatial predicates (section 2.2, spatial traversal). */
+typedef enum {
+  ABX_PRED_WITHIN = 0,         /* data [m,3] points; hit iff distance <= r    */
+  ABX_PRED_INTERSECTS_BOX = 1  /* data [m,6] boxes; hit iff closed boxes meet */
+} abx_pred_kind;
+
+typedef struct {
+  abx_pred_kind kind;
+  const float *data;   /* device [m,3] or [m,6]                         */
+  int64_t m;
+  const float *radii;  /* device [m] per-query radius, or NULL          */
+  float radius;        /* used when radii == NULL; r < 0 gives no hits  */
+  int32_t sort_queries;/* 1: traverse in Morton order of the queries
+                          (section 2.2 "Query ordering"); 0: input order */
+} abx_predicates;
+
+typedef struct abx_bvh abx_bvh; /* opaque host handle */
+
+/* Layout of a built tree inside the caller's tree buffer (for inspection). */
+typedef struct {
+  int64_t n;              /* number of primitives (leaves)                  */
+  int32_t kind;           /* abx_prim_kind                                  */
+  int32_t node_format;    /* abx_node_format                                */
+  int32_t morton_bits;
+  int32_t height;         /* longest root-to-leaf edge count (0 if n <= 1)  */
+  float scene[6];         /* scene box lo xyz, hi xyz (section 2.1)         */
+  size_t nodes_offset;    /* byte offset of internal node 0 in tree memory */
+  size_t node_bytes;      /* 64 (FP32) or 32 (Q16)                          */
+  size_t leaves_offset;   /* byte offset of leaf 0                          */
+  size_t leaf_bytes;      /* 4 (FP32: int32 permutation index) or 16/32 (Q16:
+                             float xyz + int32 index / float lo,hi + index)  */
+  float q16_origin[3];    /* Q16 dequantisation: x = fmaf(q, scale, origin) */
+  float q16_scale[3];
+} abx_bvh_layout;
+
+/* -- construction (section 2.1) ------------------------------------------
+ * abx_bvh_build_sizes: device bytes the tree and the build's scratch need.
+ * abx_bvh_build: builds the LBVH of `prims` into `tree_mem`.  Steps, all on
+ *   `stream`: scene box reduction with a NaN/Inf check, Morton codes of the
+ *   box centroids scaled by the scene box, stable LSD radix sort of (code,
+ *   index), Karras (2012) hierarchy over the index-augmented codes, atomic
+ *   bottom-up refit of the internal boxes (and quantisation for Q16).
+ *   Blocks the host once at the end to read the NaN flag and tree height.
+ *   Returns ABX_ERR_INVALID_INPUT for NaN/Inf coordinates (no handle).
+ *   `*out` receives a new handle; release it with abx_bvh_destroy.
+ * abx_bvh_destroy: frees the host handle only (tree memory is the caller's). */
+abx_status abx_bvh_build_sizes(const abx_primitives *prims, const abx_build_options *opts,
+                               size_t *tree_bytes /*host*/, size_t *scratch_bytes /*host*/);
+abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *opts,
+                         void *tree_mem, size_t tree_bytes, void *scratch, size_t scratch_bytes,
+                         abx_stream_t stream, abx_bvh **out /*host*/);
+abx_status abx_bvh_destroy(abx_bvh *bvh);
+abx_status abx_bvh_get_layout(const abx_bvh *bvh, abx_bvh_layout *out /*host*/);
+
+/* -- spatial queries (section 2.2 spatial traversal, 2P count-and-fill) ---
+ * abx_query_spatial_sizes: scratch bytes for a batch of m predicates.
+ * abx_query_spatial: orders the queries (optional), counts the hits of each
+ *   query by a stack traversal, scans the counts into offsets[0..m] (rows in
+ *   the caller's query order, offsets[0] = 0, offsets[m] = total), and
+ *   blocks the host to read the total into *total.  If total <= capacity it
+ *   traverses again, writing each row's primitive indices (order within a
+ *   row unspecified), and returns ABX_OK.  Otherwise it returns
+ *   ABX_ERR_CAPACITY with offsets and *total valid; the caller may then call
+ *   abx_query_spatial_fill with a large enough `indices` and the same
+ *   scratch (which keeps the query order).  total >= 2^31 gives
+ *   ABX_ERR_OVERFLOW.  The user-side estimate `capacity` plays the role of
+ *   the paper's buffer_size (section 2.3).
+ * abx_query_spatial_fill: the second pass alone, after a call of
+ *   abx_query_spatial on the same predicates and scratch. */
+abx_status abx_query_spatial_sizes(const abx_bvh *bvh, const abx_predicates *preds,
+                                   size_t *scratch_bytes /*host*/);
+abx_status abx_query_spatial(const abx_bvh *bvh, const abx_predicates *preds, void *scratch,
+                             size_t scratch_bytes, int32_t *offsets /*[m+1]*/, int32_t *indices,
+                             int64_t capacity, int64_t *total /*host*/, abx_stream_t stream);
+abx_status abx_query_spatial_fill(const abx_bvh *bvh, const abx_predicates *preds, void *scratch,
+                                  size_t scratch_bytes, const int32_t *offsets, int32_t *indices,
+                                  int64_t capacity, abx_stream_t stream);
+
+/* -- nearest queries (section 2.2 nearest traversal) ----------------------
+ * abx_query_nearest: for each of the m query points, the min(k, n) nearest
+ *   primitives by (distance, index), ascending (distance ties go to the
+ *   smaller index); missing results are purged, so every row has length
+ *   k' = min(k, n).  offsets[i] = i * k'; indices and distances are [m, k']
+ *   in the caller's query order; distances are float32 Euclidean (point to
+ *   box for box primitives).  No host synchronisation.  1 <= k <= 32 runs
+ *   the register-resident kernels; larger k returns ABX_ERR_UNSUPPORTED. */
+abx_status abx_query_nearest_sizes(const abx_bvh *bvh, int64_t m, int32_t k,
+                                   size_t *scratch_bytes /*host*/);
+abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, int64_t m,
+                             int32_t k, int32_t sort_queries, void *scratch, size_t scratch_bytes,
+                             int32_t *offsets /*[m+1]*/, int32_t *indices, float *distances,
+                             abx_stream_t stream);
+
+/* -- traversal statistics ---------------------------------------------------
+ * Same traversals run in a counting mode: stats[2*i] = internal nodes
+ * visited by query i (caller's order), stats[2*i+1] = leaf records read.
+ * Used to derive the algorithmic bytes of a batch. */
+abx_status abx_query_spatial_stats(const abx_bvh *bvh, const abx_predicates *preds,
+                                   void *scratch, size_t scratch_bytes, int32_t *stats /*[2m]*/,
+                                   abx_stream_t stream);
+abx_status abx_query_nearest_stats(const abx_bvh *bvh, const float *points, int64_t m,
+                                   int32_t k, int32_t sort_queries, void *scratch,
+                                   size_t scratch_bytes, int32_t *stats /*[2m]*/,
+                                   abx_stream_t stream);
+
+/* -- building blocks, exported for kernel-level checks ---------------------
+ * abx_morton_codes: codes of n primitives against a device scene box
+ *   (float[6]) with `bits` bits per axis (10 or 21): centroid, scaled into
+ *   [0,1]^3 in float32 (inverse extent, clamp), quantised, interleaved with
+ *   x as the most significant bit of each triple (section 2.1).
+ * abx_radix_sort_pairs: stable LSD radix sort of n (key, value) pairs on the
+ *   low `key_bits` bits (keys uint32 when key_bits <= 32, else uint64;
+ *   values int32, or the identity 0..n-1 when vals_in is NULL). */
+abx_status abx_morton_codes(abx_prim_kind kind, const float *prims, int64_t n, const float *scene,
+                            int32_t bits, uint64_t *codes, abx_stream_t stream);
+abx_status abx_radix_sort_sizes(int64_t n, int32_t key_bits, size_t *scratch_bytes /*host*/);
+abx_status abx_radix_sort_pairs(const void *keys_in, const int32_t *vals_in, int64_t n,
+                                int32_t key_bits, void *keys_out, int32_t *vals_out,
+                                void *scratch, size_t scratch_bytes, abx_stream_t stream);
+
+/* -- diagnostics -------------------------------------------------------------
+ * abx_timing_enable(1) brackets every kernel launch with HIP events on the
+ *   launch stream; abx_timing_get(name) returns the summed milliseconds and
+ *   launch count of the kernels called `name` since the last reset (the
+ *   host waits on the events).  Not thread safe; for measurement only. */
+const char *abx_status_string(abx_status s);
+int abx_last_hip_error(void);
+const char *abx_version(void);
+void abx_timing_enable(int on);
+void abx_timing_reset(void);
+abx_status abx_timing_get(const char *kernel, double *ms /*host*/, int64_t *launches /*host*/);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABX_H */

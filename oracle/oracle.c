@@ -73,8 +73,9 @@ static void prim_box(const float *p, int kind, int64_t i, float lo[3], float hi[
 
 /* ---------------------------------------------------------------------------
  * Scene box: reduction of the corners of all primitive boxes (section 2.1).
- * Returns 1 if any coordinate is NaN or infinite (then `out` is unspecified),
- * else 0.  n = 0 gives the empty box lo = +inf, hi = -inf.
+ * Returns 1 if any coordinate is NaN or infinite, or a box has lo > hi on
+ * some axis (then `out` is unspecified), else 0.  n = 0 gives the empty box
+ * lo = +inf, hi = -inf.
  * ------------------------------------------------------------------------- */
 int oracle_scene_box(const float *prims, int64_t n, int kind, float out[6]) {
   for (int a = 0; a < 3; ++a) {
@@ -86,7 +87,7 @@ int oracle_scene_box(const float *prims, int64_t n, int kind, float out[6]) {
     float lo[3], hi[3];
     prim_box(prims, kind, i, lo, hi);
     for (int a = 0; a < 3; ++a) {
-      if (!isfinite(lo[a]) || !isfinite(hi[a])) bad = 1;
+      if (!isfinite(lo[a]) || !isfinite(hi[a]) || lo[a] > hi[a]) bad = 1;
       if (lo[a] < out[a]) out[a] = lo[a];
       if (hi[a] > out[3 + a]) out[3 + a] = hi[a];
     }

@@ -1,0 +1,349 @@
+"""Python binding of libabx (ctypes), argument marshalling only.
+
+Every step of construction and search runs in the library's HIP kernels; this
+module allocates device buffers with PyTorch (the library never allocates),
+passes raw device pointers and the current HIP stream, and maps status codes
+to exceptions.  If ``libabx.so`` is missing or cannot be loaded, every call
+raises -- there is no fallback.
+
+Entry points (same names as the C-ABI, ``abx_`` prefix dropped):
+
+* ``bvh_build(prims, kind=None, node_format="fp32", morton_bits=21) -> BVH``
+* ``query_spatial(bvh, data, radius=..., radii=None, predicate="within",
+  sort_queries=True, capacity=None) -> (offsets, indices)``
+* ``query_nearest(bvh, points, k, sort_queries=True) -> (offsets, indices, distances)``
+* ``query_spatial_stats`` / ``query_nearest_stats`` -> int32 [m, 2]
+* ``morton_codes``, ``radix_sort_pairs`` (building blocks)
+* ``timing_enable``, ``timing_reset``, ``timing_get``
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabx.so")
+
+# status codes (include/abx.h)
+OK, ERR_INVALID_ARG, ERR_INVALID_INPUT, ERR_CAPACITY, ERR_OVERFLOW, ERR_HIP, ERR_UNSUPPORTED = range(7)
+PRIM_POINTS, PRIM_BOXES = 0, 1
+NODES_FP32, NODES_Q16 = 0, 1
+PRED_WITHIN, PRED_INTERSECTS_BOX = 0, 1
+
+_FORMATS = {"fp32": NODES_FP32, "q16": NODES_Q16, NODES_FP32: NODES_FP32, NODES_Q16: NODES_Q16}
+_PREDS = {"within": PRED_WITHIN, "intersects": PRED_INTERSECTS_BOX,
+          PRED_WITHIN: PRED_WITHIN, PRED_INTERSECTS_BOX: PRED_INTERSECTS_BOX}
+
+
+class AbxError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = _lib().abx_status_string(status).decode() if _LIB is not None else str(status)
+        extra = ""
+        if status == ERR_HIP and _LIB is not None:
+            extra = f" (hip error {_LIB.abx_last_hip_error()})"
+        super().__init__(f"{where}: {msg}{extra}")
+
+
+class Primitives(C.Structure):
+    _fields_ = [("kind", C.c_int), ("data", C.c_void_p), ("n", C.c_int64)]
+
+
+class BuildOptions(C.Structure):
+    _fields_ = [("node_format", C.c_int), ("morton_bits", C.c_int32)]
+
+
+class Predicates(C.Structure):
+    _fields_ = [("kind", C.c_int), ("data", C.c_void_p), ("m", C.c_int64), ("radii", C.c_void_p),
+                ("radius", C.c_float), ("sort_queries", C.c_int32)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("n", C.c_int64), ("kind", C.c_int32), ("node_format", C.c_int32),
+                ("morton_bits", C.c_int32), ("height", C.c_int32), ("scene", C.c_float * 6),
+                ("nodes_offset", C.c_size_t), ("node_bytes", C.c_size_t),
+                ("leaves_offset", C.c_size_t), ("leaf_bytes", C.c_size_t),
+                ("q16_origin", C.c_float * 3), ("q16_scale", C.c_float * 3)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libabx.so not built ({LIB_PATH}); run "
+                               "`python -m paper_1908_11807_amd.build` (needs ROCm hipcc)")
+        L = C.CDLL(LIB_PATH)
+        vp, sz, i64, i32 = C.c_void_p, C.c_size_t, C.c_int64, C.c_int32
+        P = C.POINTER
+        sig = {
+            "abx_bvh_build_sizes": [P(Primitives), P(BuildOptions), P(sz), P(sz)],
+            "abx_bvh_build": [P(Primitives), P(BuildOptions), vp, sz, vp, sz, vp, P(vp)],
+            "abx_bvh_destroy": [vp],
+            "abx_bvh_get_layout": [vp, P(Layout)],
+            "abx_query_spatial_sizes": [vp, P(Predicates), P(sz)],
+            "abx_query_spatial": [vp, P(Predicates), vp, sz, vp, vp, i64, P(i64), vp],
+            "abx_query_spatial_fill": [vp, P(Predicates), vp, sz, vp, vp, i64, vp],
+            "abx_query_nearest_sizes": [vp, i64, i32, P(sz)],
+            "abx_query_nearest": [vp, vp, i64, i32, i32, vp, sz, vp, vp, vp, vp],
+            "abx_query_spatial_stats": [vp, P(Predicates), vp, sz, vp, vp],
+            "abx_query_nearest_stats": [vp, vp, i64, i32, i32, vp, sz, vp, vp],
+            "abx_morton_codes": [C.c_int, vp, i64, vp, i32, vp, vp],
+            "abx_radix_sort_sizes": [i64, i32, P(sz)],
+            "abx_radix_sort_pairs": [vp, vp, i64, i32, vp, vp, vp, sz, vp],
+            "abx_timing_get": [C.c_char_p, P(C.c_double), P(i64)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.abx_status_string.argtypes = [C.c_int]
+        L.abx_status_string.restype = C.c_char_p
+        L.abx_version.restype = C.c_char_p
+        L.abx_last_hip_error.restype = C.c_int
+        L.abx_timing_enable.argtypes = [C.c_int]
+        L.abx_timing_enable.restype = None
+        L.abx_timing_reset.restype = None
+        _LIB = L
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _lib()
+
+
+def _check(st, where):
+    if st != OK:
+        raise AbxError(st, where)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+def _dev_f32(x, width, what):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{what} must be float32")
+    x = x.contiguous()
+    if x.numel() % width:
+        raise ValueError(f"{what} must have {width} columns")
+    return x.view(-1, width)
+
+
+def _bytes(n, device):
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+class BVH:
+    """A built tree: the device tree buffer (torch) plus the library handle."""
+
+    def __init__(self, handle, tree, prims, kind):
+        self._h = handle
+        self.tree = tree
+        self.prims = prims      # keeps the primitives alive for the tree's lifetime
+        self.kind = kind
+        lay = Layout()
+        _check(_lib().abx_bvh_get_layout(self._h, C.byref(lay)), "abx_bvh_get_layout")
+        self.layout = lay
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n(self):
+        return int(self.layout.n)
+
+    @property
+    def height(self):
+        return int(self.layout.height)
+
+    @property
+    def node_format(self):
+        return int(self.layout.node_format)
+
+    @property
+    def scene(self):
+        return list(self.layout.scene)
+
+    def nodes_bytes(self):
+        lay = self.layout
+        ni = max(self.n - 1, 0)
+        return self.tree[lay.nodes_offset: lay.nodes_offset + ni * lay.node_bytes]
+
+    def leaves_bytes(self):
+        lay = self.layout
+        return self.tree[lay.leaves_offset: lay.leaves_offset + self.n * lay.leaf_bytes]
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            _LIB.abx_bvh_destroy(h)
+
+
+def bvh_build(prims, kind=None, node_format="fp32", morton_bits=21):
+    """Build the LBVH of ``prims`` (float32 CUDA tensor, [n,3] points or [n,6] boxes)."""
+    L = _lib()
+    if kind is None:
+        kind = PRIM_BOXES if (prims.dim() == 2 and prims.shape[-1] == 6) else PRIM_POINTS
+    width = 3 if kind == PRIM_POINTS else 6
+    p = _dev_f32(prims, width, "primitives")
+    pr = Primitives(kind, p.data_ptr() if p.numel() else None, p.shape[0])
+    opt = BuildOptions(_FORMATS[node_format], int(morton_bits))
+    tb, sb = C.c_size_t(), C.c_size_t()
+    _check(L.abx_bvh_build_sizes(C.byref(pr), C.byref(opt), C.byref(tb), C.byref(sb)),
+           "abx_bvh_build_sizes")
+    tree = _bytes(tb.value, p.device)
+    scratch = _bytes(sb.value, p.device)
+    h = C.c_void_p()
+    _check(L.abx_bvh_build(C.byref(pr), C.byref(opt), _ptr(tree), tb.value, _ptr(scratch), sb.value,
+                           _stream(), C.byref(h)), "abx_bvh_build")
+    return BVH(h, tree, p, kind)
+
+
+def _preds(data, predicate, radius, radii, sort_queries):
+    kind = _PREDS[predicate]
+    width = 3 if kind == PRED_WITHIN else 6
+    d = _dev_f32(data, width, "query data")
+    rr = None
+    if radii is not None:
+        rr = _dev_f32(radii, 1, "radii").view(-1)
+        if rr.shape[0] != d.shape[0]:
+            raise ValueError("radii must have one entry per query")
+    pr = Predicates(kind, d.data_ptr() if d.numel() else None, d.shape[0],
+                    rr.data_ptr() if rr is not None and rr.numel() else None,
+                    float(radius if radius is not None else 0.0), 1 if sort_queries else 0)
+    return pr, d, rr
+
+
+def query_spatial(bvh, data, radius=None, radii=None, predicate="within", sort_queries=True,
+                  capacity=None):
+    """Spatial predicates -> CSR (offsets int32 [m+1], indices int32 [total]).
+
+    Two-pass count-and-fill.  ``capacity`` is the caller's estimate of the
+    total number of results (the paper's buffer_size); when it is missing or
+    too small the exact total is allocated after the counting pass.
+    """
+    L = _lib()
+    pr, d, rr = _preds(data, predicate, radius, radii, sort_queries)
+    m = d.shape[0]
+    sb = C.c_size_t()
+    _check(L.abx_query_spatial_sizes(bvh.handle, C.byref(pr), C.byref(sb)), "abx_query_spatial_sizes")
+    scratch = _bytes(sb.value, d.device)
+    offsets = torch.empty(m + 1, dtype=torch.int32, device=d.device)
+    cap = int(capacity or 0)
+    indices = torch.empty(max(cap, 1), dtype=torch.int32, device=d.device)
+    total = C.c_int64()
+    st = L.abx_query_spatial(bvh.handle, C.byref(pr), _ptr(scratch), sb.value, _ptr(offsets),
+                             _ptr(indices) if cap > 0 else C.c_void_p(0), cap, C.byref(total),
+                             _stream())
+    if st == ERR_CAPACITY:
+        indices = torch.empty(max(total.value, 1), dtype=torch.int32, device=d.device)
+        st = L.abx_query_spatial_fill(bvh.handle, C.byref(pr), _ptr(scratch), sb.value,
+                                      _ptr(offsets), _ptr(indices), total.value, _stream())
+    _check(st, "abx_query_spatial")
+    return offsets, indices[: total.value]
+
+
+def query_nearest(bvh, points, k, sort_queries=True):
+    """k nearest primitives of each point -> (offsets, indices [m,k'], distances [m,k'])."""
+    L = _lib()
+    q = _dev_f32(points, 3, "query points")
+    m = q.shape[0]
+    kk = max(0, min(int(k), bvh.n))
+    sb = C.c_size_t()
+    _check(L.abx_query_nearest_sizes(bvh.handle, m, int(k), C.byref(sb)), "abx_query_nearest_sizes")
+    scratch = _bytes(sb.value, q.device)
+    offsets = torch.empty(m + 1, dtype=torch.int32, device=q.device)
+    idx = torch.empty((m, kk), dtype=torch.int32, device=q.device)
+    dist = torch.empty((m, kk), dtype=torch.float32, device=q.device)
+    _check(L.abx_query_nearest(bvh.handle, _ptr(q), m, int(k), 1 if sort_queries else 0,
+                               _ptr(scratch), sb.value, _ptr(offsets), _ptr(idx), _ptr(dist),
+                               _stream()), "abx_query_nearest")
+    return offsets, idx, dist
+
+
+def query_spatial_stats(bvh, data, radius=None, radii=None, predicate="within", sort_queries=True):
+    """Per query: (internal nodes visited, leaf records read), int32 [m, 2]."""
+    L = _lib()
+    pr, d, rr = _preds(data, predicate, radius, radii, sort_queries)
+    sb = C.c_size_t()
+    _check(L.abx_query_spatial_sizes(bvh.handle, C.byref(pr), C.byref(sb)), "abx_query_spatial_sizes")
+    scratch = _bytes(sb.value, d.device)
+    stats = torch.empty((d.shape[0], 2), dtype=torch.int32, device=d.device)
+    _check(L.abx_query_spatial_stats(bvh.handle, C.byref(pr), _ptr(scratch), sb.value, _ptr(stats),
+                                     _stream()), "abx_query_spatial_stats")
+    return stats
+
+
+def query_nearest_stats(bvh, points, k, sort_queries=True):
+    L = _lib()
+    q = _dev_f32(points, 3, "query points")
+    sb = C.c_size_t()
+    _check(L.abx_query_nearest_sizes(bvh.handle, q.shape[0], int(k), C.byref(sb)),
+           "abx_query_nearest_sizes")
+    scratch = _bytes(sb.value, q.device)
+    stats = torch.empty((q.shape[0], 2), dtype=torch.int32, device=q.device)
+    _check(L.abx_query_nearest_stats(bvh.handle, _ptr(q), q.shape[0], int(k),
+                                     1 if sort_queries else 0, _ptr(scratch), sb.value,
+                                     _ptr(stats), _stream()), "abx_query_nearest_stats")
+    return stats
+
+
+def morton_codes(prims, scene, bits, kind=None):
+    """Morton codes (int64 tensor holding the uint64 codes) against a scene box."""
+    L = _lib()
+    if kind is None:
+        kind = PRIM_BOXES if prims.shape[-1] == 6 else PRIM_POINTS
+    p = _dev_f32(prims, 3 if kind == PRIM_POINTS else 6, "primitives")
+    sc = _dev_f32(scene, 6, "scene").view(-1)
+    codes = torch.empty(p.shape[0], dtype=torch.int64, device=p.device)
+    _check(L.abx_morton_codes(kind, _ptr(p), p.shape[0], _ptr(sc), int(bits), _ptr(codes), _stream()),
+           "abx_morton_codes")
+    return codes
+
+
+def radix_sort_pairs(keys, key_bits, vals=None):
+    """Stable radix sort of (key, value) pairs; keys int32 (<=32 bits) or int64."""
+    L = _lib()
+    n = keys.numel()
+    keys = keys.contiguous()
+    sb = C.c_size_t()
+    _check(L.abx_radix_sort_sizes(n, int(key_bits), C.byref(sb)), "abx_radix_sort_sizes")
+    scratch = _bytes(sb.value, keys.device)
+    kout = torch.empty_like(keys)
+    vout = torch.empty(n, dtype=torch.int32, device=keys.device)
+    vin = None if vals is None else vals.contiguous()
+    _check(L.abx_radix_sort_pairs(_ptr(keys), _ptr(vin), n, int(key_bits), _ptr(kout), _ptr(vout),
+                                  _ptr(scratch), sb.value, _stream()), "abx_radix_sort_pairs")
+    return kout, vout
+
+
+def timing_enable(on=True):
+    _lib().abx_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    _lib().abx_timing_reset()
+
+
+def timing_get(name):
+    """(milliseconds summed, launches) of kernels called ``name`` since the last reset."""
+    ms, cnt = C.c_double(), C.c_int64()
+    _check(_lib().abx_timing_get(name.encode(), C.byref(ms), C.byref(cnt)), "abx_timing_get")
+    return ms.value, cnt.value
+
+
+def version():
+    return _lib().abx_version().decode()

@@ -1,0 +1,504 @@
+// C-ABI of libabx: argument validation, buffer layout, the launch sequence of
+// each entry point and the diagnostics.  No device memory is allocated here.
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "abx_internal.h"
+
+namespace abx {
+
+// build.hip
+abx_status launch_scene(int kind, const float *prims, int64_t n, float *partial, int blocks,
+                        TreeHeader *hdr, hipStream_t s);
+int scene_blocks(int64_t n);
+abx_status launch_morton(int kind, const float *prims, int64_t n, const float *scene, int bits,
+                         void *codes, bool wide, hipStream_t s);
+abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
+                         int32_t *parent_leaf, int32_t *parent_int, uint32_t *flags, hipStream_t s);
+abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
+                        const int32_t *parent_leaf, const int32_t *parent_int, NodeF32 *nodes,
+                        uint32_t *flags, TreeHeader *hdr, void *q16_leaves, hipStream_t s);
+abx_status launch_quantise(const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
+                           hipStream_t s);
+// traverse.hip
+abx_status launch_query_codes(const abx_bvh *b, const float *q, int64_t m, int width,
+                              uint32_t *codes, hipStream_t s);
+abx_status launch_spatial(const abx_bvh *b, int pred, const float *data, int64_t m,
+                          const float *radii, float radius, const int32_t *order, int mode,
+                          int32_t *counts, const int32_t *offsets, int32_t *indices, hipStream_t s);
+abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order,
+                          int k, int32_t *idx, float *dist, int32_t *stats, hipStream_t s);
+int max_tree_depth();
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+struct Pending {
+  std::string name;
+  hipEvent_t a, b;
+};
+bool g_timing = false;
+std::vector<Pending> g_pending;
+std::map<std::string, std::pair<double, int64_t>> g_acc;
+
+constexpr int64_t kMaxCount = INT32_MAX;
+
+__global__ void k_row_offsets(int32_t *off, int64_t m, int32_t k) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= m) off[i] = (int32_t)(i * k);
+}
+
+abx_status row_offsets(int32_t *off, int64_t m, int32_t k, hipStream_t s) {
+  return launch("row_offsets", s, [&] {
+    k_row_offsets<<<grid_for(m + 1, 256), 256, 0, s>>>(off, m, k);
+  });
+}
+
+// ---------------------------------------------------------------- build
+struct BuildLayout {
+  int64_t n, ni;
+  bool wide, q16;
+  int bits;
+  size_t node_bytes, leaf_bytes;
+  size_t nodes_off, leaves_off, tree_total;
+  // scratch
+  size_t partial, codes, sorted, perm, parent_leaf, parent_int, flags, staging, sort, scratch_total;
+};
+
+int resolve_bits(const abx_build_options *o) { return (o == nullptr || o->morton_bits == 0) ? 21 : o->morton_bits; }
+
+abx_status check_build_args(const abx_primitives *p, const abx_build_options *o) {
+  if (!p) return ABX_ERR_INVALID_ARG;
+  if (p->kind != ABX_PRIM_POINTS && p->kind != ABX_PRIM_BOXES) return ABX_ERR_INVALID_ARG;
+  if (p->n < 0) return ABX_ERR_INVALID_ARG;
+  if (p->n >= kMaxCount) return ABX_ERR_OVERFLOW;
+  if (p->n > 0 && !p->data) return ABX_ERR_INVALID_ARG;
+  if (o && o->node_format != ABX_NODES_FP32 && o->node_format != ABX_NODES_Q16)
+    return ABX_ERR_INVALID_ARG;
+  const int bits = resolve_bits(o);
+  if (bits != 10 && bits != 21) return ABX_ERR_INVALID_ARG;
+  return ABX_OK;
+}
+
+BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
+  BuildLayout L{};
+  L.n = p->n;
+  L.ni = p->n > 1 ? p->n - 1 : 0;
+  L.bits = resolve_bits(o);
+  L.wide = L.bits > 10;
+  L.q16 = o && o->node_format == ABX_NODES_Q16;
+  L.node_bytes = L.q16 ? sizeof(NodeQ16) : sizeof(NodeF32);
+  L.leaf_bytes = L.q16 ? (p->kind == ABX_PRIM_POINTS ? 16 : 32) : 4;
+  size_t off = sizeof(TreeHeader);
+  L.nodes_off = off;
+  off = align_up(off + (size_t)L.ni * L.node_bytes, 256);
+  L.leaves_off = off;
+  off = align_up(off + (size_t)L.n * L.leaf_bytes, 256);
+  L.tree_total = off;
+
+  const size_t ksz = L.wide ? 8 : 4;
+  const size_t n = (size_t)L.n;
+  off = 0;
+  L.partial = off;
+  off = align_up(off + 1024 * 8 * sizeof(float), 256);
+  L.codes = off;
+  off = align_up(off + n * ksz, 256);
+  L.sorted = off;
+  off = align_up(off + n * ksz, 256);
+  L.perm = off;
+  off = align_up(off + (L.q16 ? n * 4 : 0), 256);
+  L.parent_leaf = off;
+  off = align_up(off + n * 4, 256);
+  L.parent_int = off;
+  off = align_up(off + n * 4, 256);
+  L.flags = off;
+  off = align_up(off + n * 4, 256);
+  L.staging = off;
+  off = align_up(off + (L.q16 ? (size_t)L.ni * sizeof(NodeF32) : 0), 256);
+  L.sort = off;
+  off = align_up(off + radix_sort_scratch_bytes(L.n, 3 * L.bits), 256);
+  L.scratch_total = off;
+  return L;
+}
+
+// ---------------------------------------------------------------- queries
+struct QueryLayout {
+  size_t codes, sorted, order, counts, total, scan, sort, bytes;
+};
+
+QueryLayout query_layout(int64_t m) {
+  QueryLayout L{};
+  const size_t mm = (size_t)m;
+  size_t off = 0;
+  L.codes = off;
+  off = align_up(off + mm * 4, 256);
+  L.sorted = off;
+  off = align_up(off + mm * 4, 256);
+  L.order = off;
+  off = align_up(off + mm * 4, 256);
+  L.counts = off;
+  off = align_up(off + mm * 4, 256);
+  L.total = off;
+  off = align_up(off + 8, 256);
+  L.scan = off;
+  off = align_up(off + scan_scratch_bytes(m), 256);
+  L.sort = off;
+  off = align_up(off + radix_sort_scratch_bytes(m, 30), 256);
+  L.bytes = off;
+  return L;
+}
+
+abx_status check_bvh(const abx_bvh *b) { return b ? ABX_OK : ABX_ERR_INVALID_ARG; }
+
+abx_status check_preds(const abx_predicates *p) {
+  if (!p) return ABX_ERR_INVALID_ARG;
+  if (p->kind != ABX_PRED_WITHIN && p->kind != ABX_PRED_INTERSECTS_BOX) return ABX_ERR_INVALID_ARG;
+  if (p->m < 0) return ABX_ERR_INVALID_ARG;
+  if (p->m >= kMaxCount) return ABX_ERR_OVERFLOW;
+  if (p->m > 0 && !p->data) return ABX_ERR_INVALID_ARG;
+  return ABX_OK;
+}
+
+// queries in Morton order: order[] = permutation sorted position -> query
+abx_status order_queries(const abx_bvh *b, const float *data, int64_t m, int width, char *scratch,
+                         const QueryLayout &L, const int32_t **order, hipStream_t s) {
+  uint32_t *codes = reinterpret_cast<uint32_t *>(scratch + L.codes);
+  int32_t *ord = reinterpret_cast<int32_t *>(scratch + L.order);
+  ABX_TRY(launch_query_codes(b, data, m, width, codes, s));
+  ABX_TRY(radix_sort(codes, nullptr, m, 30, scratch + L.sorted, ord, scratch + L.sort,
+                     radix_sort_scratch_bytes(m, 30), s));
+  *order = ord;
+  return ABX_OK;
+}
+
+}  // namespace
+
+abx_status hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return ABX_ERR_HIP;
+}
+
+bool timing_on() { return g_timing; }
+
+void timing_record(const char *name, hipEvent_t a, hipEvent_t b) {
+  g_pending.push_back(Pending{name, a, b});
+}
+
+}  // namespace abx
+
+using namespace abx;
+
+extern "C" {
+
+const char *abx_version(void) { return "abx 0.1 (gfx950)"; }
+
+const char *abx_status_string(abx_status s) {
+  switch (s) {
+    case ABX_OK: return "ok";
+    case ABX_ERR_INVALID_ARG: return "invalid argument";
+    case ABX_ERR_INVALID_INPUT: return "invalid input (NaN/Inf coordinate or inverted box)";
+    case ABX_ERR_CAPACITY: return "result buffer too small";
+    case ABX_ERR_OVERFLOW: return "size or result count reaches 2^31";
+    case ABX_ERR_HIP: return "HIP runtime error";
+    case ABX_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+int abx_last_hip_error(void) { return g_last_hip; }
+
+void abx_timing_enable(int on) { g_timing = on != 0; }
+
+static void timing_flush() {
+  for (auto &p : g_pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto &acc = g_acc[p.name];
+      acc.first += ms;
+      acc.second += 1;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_pending.clear();
+}
+
+void abx_timing_reset(void) {
+  timing_flush();
+  g_acc.clear();
+}
+
+abx_status abx_timing_get(const char *kernel, double *ms, int64_t *launches) {
+  if (!kernel || !ms || !launches) return ABX_ERR_INVALID_ARG;
+  timing_flush();
+  auto it = g_acc.find(kernel);
+  *ms = it == g_acc.end() ? 0.0 : it->second.first;
+  *launches = it == g_acc.end() ? 0 : it->second.second;
+  return ABX_OK;
+}
+
+// ---------------------------------------------------------------- build
+abx_status abx_bvh_build_sizes(const abx_primitives *prims, const abx_build_options *opts,
+                               size_t *tree_bytes, size_t *scratch_bytes) {
+  ABX_TRY(check_build_args(prims, opts));
+  if (!tree_bytes || !scratch_bytes) return ABX_ERR_INVALID_ARG;
+  const BuildLayout L = build_layout(prims, opts);
+  *tree_bytes = L.tree_total;
+  *scratch_bytes = L.scratch_total;
+  return ABX_OK;
+}
+
+abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *opts,
+                         void *tree_mem, size_t tree_bytes, void *scratch, size_t scratch_bytes,
+                         abx_stream_t stream, abx_bvh **out) {
+  ABX_TRY(check_build_args(prims, opts));
+  if (!out || !tree_mem || !scratch) return ABX_ERR_INVALID_ARG;
+  *out = nullptr;
+  const BuildLayout L = build_layout(prims, opts);
+  if (tree_bytes < L.tree_total || scratch_bytes < L.scratch_total) return ABX_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(tree_mem) | reinterpret_cast<uintptr_t>(scratch)) & 255)
+    return ABX_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *tree = static_cast<char *>(tree_mem);
+  char *sc = static_cast<char *>(scratch);
+  TreeHeader *hdr = reinterpret_cast<TreeHeader *>(tree);
+  const int64_t n = L.n;
+  const int kind = prims->kind;
+
+  const int blocks = scene_blocks(n);
+  ABX_TRY(launch_scene(kind, prims->data, n, reinterpret_cast<float *>(sc + L.partial), blocks, hdr, s));
+  int32_t *perm = L.q16 ? reinterpret_cast<int32_t *>(sc + L.perm)
+                        : reinterpret_cast<int32_t *>(tree + L.leaves_off);
+  NodeF32 *fnodes = L.q16 ? reinterpret_cast<NodeF32 *>(sc + L.staging)
+                          : reinterpret_cast<NodeF32 *>(tree + L.nodes_off);
+  int32_t *parent_leaf = reinterpret_cast<int32_t *>(sc + L.parent_leaf);
+  int32_t *parent_int = reinterpret_cast<int32_t *>(sc + L.parent_int);
+  uint32_t *flags = reinterpret_cast<uint32_t *>(sc + L.flags);
+  if (n > 0) {
+    ABX_TRY(launch_morton(kind, prims->data, n, hdr->scene, L.bits, sc + L.codes, L.wide, s));
+    ABX_TRY(radix_sort(sc + L.codes, nullptr, n, 3 * L.bits, sc + L.sorted, perm, sc + L.sort,
+                       radix_sort_scratch_bytes(n, 3 * L.bits), s));
+    ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, fnodes, parent_leaf, parent_int, flags, s));
+    ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, parent_leaf, parent_int, fnodes, flags,
+                         hdr, tree + L.leaves_off, s));
+    if (L.q16)
+      ABX_TRY(launch_quantise(fnodes, L.ni, hdr, reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
+  }
+  TreeHeader h;
+  ABX_HIP(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+  ABX_HIP(hipStreamSynchronize(s));
+  if (h.bad & 1) return ABX_ERR_INVALID_INPUT;
+  if (h.bad & 4) return ABX_ERR_UNSUPPORTED;  // refit bound exceeded (malformed hierarchy)
+  if ((h.bad & 2) && L.q16) return ABX_ERR_UNSUPPORTED;
+  if (h.height >= max_tree_depth() - 1) return ABX_ERR_UNSUPPORTED;
+
+  abx_bvh *b = new (std::nothrow) abx_bvh;
+  if (!b) return ABX_ERR_INVALID_ARG;
+  b->n = n;
+  b->kind = kind;
+  b->format = L.q16 ? ABX_NODES_Q16 : ABX_NODES_FP32;
+  b->morton_bits = L.bits;
+  b->height = h.height;
+  std::memcpy(b->scene, h.scene, sizeof(b->scene));
+  std::memcpy(b->q_origin, h.q_origin, sizeof(b->q_origin));
+  std::memcpy(b->q_scale, h.q_scale, sizeof(b->q_scale));
+  b->tree = tree;
+  b->tree_bytes = tree_bytes;
+  b->nodes_off = L.nodes_off;
+  b->leaves_off = L.leaves_off;
+  b->node_bytes = L.node_bytes;
+  b->leaf_bytes = L.leaf_bytes;
+  *out = b;
+  return ABX_OK;
+}
+
+abx_status abx_bvh_destroy(abx_bvh *bvh) {
+  delete bvh;
+  return ABX_OK;
+}
+
+abx_status abx_bvh_get_layout(const abx_bvh *b, abx_bvh_layout *o) {
+  if (!b || !o) return ABX_ERR_INVALID_ARG;
+  o->n = b->n;
+  o->kind = b->kind;
+  o->node_format = b->format;
+  o->morton_bits = b->morton_bits;
+  o->height = b->height;
+  std::memcpy(o->scene, b->scene, sizeof(o->scene));
+  o->nodes_offset = b->nodes_off;
+  o->node_bytes = b->node_bytes;
+  o->leaves_offset = b->leaves_off;
+  o->leaf_bytes = b->leaf_bytes;
+  std::memcpy(o->q16_origin, b->q_origin, sizeof(o->q16_origin));
+  std::memcpy(o->q16_scale, b->q_scale, sizeof(o->q16_scale));
+  return ABX_OK;
+}
+
+// ---------------------------------------------------------------- spatial
+abx_status abx_query_spatial_sizes(const abx_bvh *bvh, const abx_predicates *preds,
+                                   size_t *scratch_bytes) {
+  ABX_TRY(check_bvh(bvh));
+  ABX_TRY(check_preds(preds));
+  if (!scratch_bytes) return ABX_ERR_INVALID_ARG;
+  *scratch_bytes = query_layout(preds->m).bytes;
+  return ABX_OK;
+}
+
+static abx_status spatial_prologue(const abx_bvh *bvh, const abx_predicates *preds, void *scratch,
+                                   size_t scratch_bytes, QueryLayout *L) {
+  ABX_TRY(check_bvh(bvh));
+  ABX_TRY(check_preds(preds));
+  *L = query_layout(preds->m);
+  if (!scratch || scratch_bytes < L->bytes) return ABX_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return ABX_ERR_INVALID_ARG;
+  return ABX_OK;
+}
+
+abx_status abx_query_spatial(const abx_bvh *bvh, const abx_predicates *preds, void *scratch,
+                             size_t scratch_bytes, int32_t *offsets, int32_t *indices,
+                             int64_t capacity, int64_t *total, abx_stream_t stream) {
+  QueryLayout L;
+  ABX_TRY(spatial_prologue(bvh, preds, scratch, scratch_bytes, &L));
+  if (!offsets || !total || capacity < 0 || (capacity > 0 && !indices)) return ABX_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *sc = static_cast<char *>(scratch);
+  const int64_t m = preds->m;
+  const int width = preds->kind == ABX_PRED_WITHIN ? 3 : 6;
+  int32_t *counts = reinterpret_cast<int32_t *>(sc + L.counts);
+  int64_t *d_total = reinterpret_cast<int64_t *>(sc + L.total);
+  *total = 0;
+  if (bvh->n == 0 || m == 0) {
+    ABX_TRY(fill_u32(offsets, 0, (size_t)m + 1, s));
+    return ABX_OK;
+  }
+  const int32_t *order = nullptr;
+  if (preds->sort_queries) ABX_TRY(order_queries(bvh, preds->data, m, width, sc, L, &order, s));
+  ABX_TRY(launch_spatial(bvh, preds->kind, preds->data, m, preds->radii, preds->radius, order,
+                         0 /*count*/, counts, nullptr, nullptr, s));
+  ABX_TRY(exclusive_scan(counts, m, offsets, d_total, sc + L.scan, scan_scratch_bytes(m), s));
+  int64_t t = 0;
+  ABX_HIP(hipMemcpyAsync(&t, d_total, sizeof(t), hipMemcpyDeviceToHost, s));
+  ABX_HIP(hipStreamSynchronize(s));
+  *total = t;
+  if (t >= kMaxCount) return ABX_ERR_OVERFLOW;
+  if (t > capacity) return ABX_ERR_CAPACITY;
+  if (t == 0) return ABX_OK;
+  return launch_spatial(bvh, preds->kind, preds->data, m, preds->radii, preds->radius, order,
+                        1 /*fill*/, nullptr, offsets, indices, s);
+}
+
+abx_status abx_query_spatial_fill(const abx_bvh *bvh, const abx_predicates *preds, void *scratch,
+                                  size_t scratch_bytes, const int32_t *offsets, int32_t *indices,
+                                  int64_t capacity, abx_stream_t stream) {
+  QueryLayout L;
+  ABX_TRY(spatial_prologue(bvh, preds, scratch, scratch_bytes, &L));
+  if (!offsets || capacity < 0 || (capacity > 0 && !indices)) return ABX_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *sc = static_cast<char *>(scratch);
+  const int64_t m = preds->m;
+  if (bvh->n == 0 || m == 0) return ABX_OK;
+  int64_t t = 0;
+  ABX_HIP(hipMemcpyAsync(&t, sc + L.total, sizeof(t), hipMemcpyDeviceToHost, s));
+  ABX_HIP(hipStreamSynchronize(s));
+  if (t > capacity) return ABX_ERR_CAPACITY;
+  if (t == 0) return ABX_OK;
+  const int32_t *order = preds->sort_queries ? reinterpret_cast<const int32_t *>(sc + L.order) : nullptr;
+  return launch_spatial(bvh, preds->kind, preds->data, m, preds->radii, preds->radius, order,
+                        1 /*fill*/, nullptr, offsets, indices, s);
+}
+
+abx_status abx_query_spatial_stats(const abx_bvh *bvh, const abx_predicates *preds, void *scratch,
+                                   size_t scratch_bytes, int32_t *stats, abx_stream_t stream) {
+  QueryLayout L;
+  ABX_TRY(spatial_prologue(bvh, preds, scratch, scratch_bytes, &L));
+  if (!stats && preds->m > 0) return ABX_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *sc = static_cast<char *>(scratch);
+  const int64_t m = preds->m;
+  if (m == 0) return ABX_OK;
+  if (bvh->n == 0) return fill_u32(stats, 0, 2 * (size_t)m, s);
+  const int width = preds->kind == ABX_PRED_WITHIN ? 3 : 6;
+  const int32_t *order = nullptr;
+  if (preds->sort_queries) ABX_TRY(order_queries(bvh, preds->data, m, width, sc, L, &order, s));
+  return launch_spatial(bvh, preds->kind, preds->data, m, preds->radii, preds->radius, order,
+                        2 /*stats*/, stats, nullptr, nullptr, s);
+}
+
+// ---------------------------------------------------------------- nearest
+abx_status abx_query_nearest_sizes(const abx_bvh *bvh, int64_t m, int32_t k, size_t *scratch_bytes) {
+  ABX_TRY(check_bvh(bvh));
+  if (m < 0 || k < 0 || !scratch_bytes) return ABX_ERR_INVALID_ARG;
+  if (m >= kMaxCount) return ABX_ERR_OVERFLOW;
+  *scratch_bytes = query_layout(m).bytes;
+  return ABX_OK;
+}
+
+static abx_status nearest_common(const abx_bvh *bvh, const float *points, int64_t m, int32_t k,
+                                 int32_t sort_queries, void *scratch, size_t scratch_bytes,
+                                 int32_t *offsets, int32_t *indices, float *distances,
+                                 int32_t *stats, abx_stream_t stream) {
+  ABX_TRY(check_bvh(bvh));
+  if (m < 0 || k < 0) return ABX_ERR_INVALID_ARG;
+  if (m >= kMaxCount) return ABX_ERR_OVERFLOW;
+  if (m > 0 && !points) return ABX_ERR_INVALID_ARG;
+  const QueryLayout L = query_layout(m);
+  if (!scratch || scratch_bytes < L.bytes || (reinterpret_cast<uintptr_t>(scratch) & 255))
+    return ABX_ERR_INVALID_ARG;
+  const int64_t kk = k < bvh->n ? k : bvh->n;
+  if (m * kk >= kMaxCount) return ABX_ERR_OVERFLOW;
+  if (kk > 32) return ABX_ERR_UNSUPPORTED;
+  if (!stats && (!offsets || (m * kk > 0 && (!indices || !distances)))) return ABX_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *sc = static_cast<char *>(scratch);
+  if (!stats) ABX_TRY(row_offsets(offsets, m, (int32_t)kk, s));
+  if (m == 0) return ABX_OK;
+  if (kk == 0) return stats ? fill_u32(stats, 0, 2 * (size_t)m, s) : ABX_OK;
+  const int32_t *order = nullptr;
+  if (sort_queries) ABX_TRY(order_queries(bvh, points, m, 3, sc, L, &order, s));
+  return launch_nearest(bvh, points, m, order, (int)kk, indices, distances, stats, s);
+}
+
+abx_status abx_query_nearest(const abx_bvh *bvh, const float *points, int64_t m, int32_t k,
+                             int32_t sort_queries, void *scratch, size_t scratch_bytes,
+                             int32_t *offsets, int32_t *indices, float *distances,
+                             abx_stream_t stream) {
+  return nearest_common(bvh, points, m, k, sort_queries, scratch, scratch_bytes, offsets, indices,
+                        distances, nullptr, stream);
+}
+
+abx_status abx_query_nearest_stats(const abx_bvh *bvh, const float *points, int64_t m, int32_t k,
+                                   int32_t sort_queries, void *scratch, size_t scratch_bytes,
+                                   int32_t *stats, abx_stream_t stream) {
+  if (!stats && m > 0) return ABX_ERR_INVALID_ARG;
+  return nearest_common(bvh, points, m, k, sort_queries, scratch, scratch_bytes, nullptr, nullptr,
+                        nullptr, stats, stream);
+}
+
+// ---------------------------------------------------------------- building blocks
+abx_status abx_morton_codes(abx_prim_kind kind, const float *prims, int64_t n, const float *scene,
+                            int32_t bits, uint64_t *codes, abx_stream_t stream) {
+  if (kind != ABX_PRIM_POINTS && kind != ABX_PRIM_BOXES) return ABX_ERR_INVALID_ARG;
+  if (n < 0 || (bits != 10 && bits != 21)) return ABX_ERR_INVALID_ARG;
+  if (n >= kMaxCount) return ABX_ERR_OVERFLOW;
+  if (n > 0 && (!prims || !scene || !codes)) return ABX_ERR_INVALID_ARG;
+  return launch_morton(kind, prims, n, scene, bits, codes, true, reinterpret_cast<hipStream_t>(stream));
+}
+
+abx_status abx_radix_sort_sizes(int64_t n, int32_t key_bits, size_t *scratch_bytes) {
+  if (n < 0 || key_bits < 1 || key_bits > 64 || !scratch_bytes) return ABX_ERR_INVALID_ARG;
+  if (n >= (int64_t)1 << 30) return ABX_ERR_OVERFLOW;
+  *scratch_bytes = radix_sort_scratch_bytes(n, key_bits);
+  return ABX_OK;
+}
+
+abx_status abx_radix_sort_pairs(const void *keys_in, const int32_t *vals_in, int64_t n,
+                                int32_t key_bits, void *keys_out, int32_t *vals_out, void *scratch,
+                                size_t scratch_bytes, abx_stream_t stream) {
+  return radix_sort(keys_in, vals_in, n, key_bits, keys_out, vals_out, scratch, scratch_bytes,
+                    reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+// Internal declarations of libabx: tree memory layout, device helpers shared
+// by the construction and traversal kernels, and the host-side launch helper.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "abx.h"
+
+namespace abx {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Tree memory (caller-owned, one buffer):
+//   [0, 256)                 TreeHeader
+//   [nodes_off, +(n-1)*NB)   internal nodes, NB = 64 (FP32) or 32 (Q16)
+//   [leaves_off, +n*LB)      leaves: FP32 -> int32 permutation index (LB=4);
+//                            Q16 points -> float4 {x,y,z,idx} (LB=16);
+//                            Q16 boxes  -> {lo xyz, hi xyz, idx, pad} (LB=32)
+// Child references: r >= 0 is internal node r, r < 0 is the leaf at sorted
+// position ~r.  Internal node 0 is the root (Karras numbering).
+// ---------------------------------------------------------------------------
+struct TreeHeader {
+  float scene[6];     // scene box lo xyz, hi xyz
+  float inv_ext[3];   // Morton normalisation: 1/(hi-lo) or 0
+  float q_origin[3];  // Q16 grid: x = fmaf(q, q_scale, q_origin)
+  float q_scale[3];
+  int32_t bad;        // 1 if a coordinate was NaN or infinite
+  int32_t height;     // longest root-to-leaf path (edges)
+  int32_t pad[47];
+};
+static_assert(sizeof(TreeHeader) == 256, "header is 256 B");
+
+// FP32 internal node, 64 B: four 16-B words
+//   a = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)
+//   b = (L.hi.y, L.hi.z, R.lo.x, R.lo.y)
+//   c = (R.lo.z, R.hi.x, R.hi.y, R.hi.z)
+//   d = (left ref, right ref, height(left), height(right))
+struct __align__(16) NodeF32 {
+  float4 a, b, c;
+  int4 d;
+};
+static_assert(sizeof(NodeF32) == 64, "fp32 node is 64 B");
+
+// Q16 internal node, 32 B: 12 uint16 coordinates then the two references
+//   w[0..5] = L.lo.xy | L.lo.z L.hi.x | L.hi.yz | R.lo.xy | R.lo.z R.hi.x | R.hi.yz
+//   (low half first), w[6] = left ref, w[7] = right ref
+struct __align__(16) NodeQ16 {
+  uint4 a, b;
+};
+static_assert(sizeof(NodeQ16) == 32, "q16 node is 32 B");
+
+constexpr int kQ16Max = 65535;
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Device helpers.  One float32 formula for the squared point-to-box distance
+// is used for internal-node boxes and leaves alike (fixed contraction: the
+// x term is a plain product, y and z are fused), so the box value never
+// exceeds the value of any primitive inside the box (rounding is monotone):
+// pruning is conservative and the result is exactly the set of leaves that
+// pass the float32 leaf test, whatever the node format.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float axis_gap(float lo, float hi, float q) {
+  return fmaxf(fmaxf(lo - q, q - hi), 0.0f);
+}
+
+__device__ __forceinline__ float box_dist2(float lx, float ly, float lz, float hx, float hy, float hz,
+                                           float qx, float qy, float qz) {
+  float gx = axis_gap(lx, hx, qx);
+  float gy = axis_gap(ly, hy, qy);
+  float gz = axis_gap(lz, hz, qz);
+  return __fmaf_rn(gz, gz, __fmaf_rn(gy, gy, gx * gx));
+}
+
+// closed-interval overlap of two boxes
+__device__ __forceinline__ bool box_overlap(float lx, float ly, float lz, float hx, float hy, float hz,
+                                            float ax, float ay, float az, float bx, float by, float bz) {
+  return lx <= bx && ax <= hx && ly <= by && ay <= hy && lz <= bz && az <= hz;
+}
+
+// Q16 dequantisation (the construction guarantees outward containment for
+// exactly this expression)
+__device__ __forceinline__ float deq(uint32_t q, float scale, float origin) {
+  return __fmaf_rn((float)q, scale, origin);
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+abx_status hip_fail(hipError_t e);  // records e for abx_last_hip_error
+bool timing_on();
+void timing_record(const char *name, hipEvent_t a, hipEvent_t b);
+
+#define ABX_TRY(expr)                         \
+  do {                                        \
+    abx_status _s = (expr);                   \
+    if (_s != ABX_OK) return _s;              \
+  } while (0)
+
+#define ABX_HIP(expr)                         \
+  do {                                        \
+    hipError_t _e = (expr);                   \
+    if (_e != hipSuccess) return hip_fail(_e);\
+  } while (0)
+
+// Launch `f` (which enqueues one kernel on `s`) and, in timing mode, bracket
+// it with events recorded on the same stream.
+template <typename F>
+abx_status launch(const char *name, hipStream_t s, F &&f) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (timing_on()) {
+    ABX_HIP(hipEventCreate(&a));
+    ABX_HIP(hipEventCreate(&b));
+    ABX_HIP(hipEventRecord(a, s));
+  }
+  f();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  if (timing_on()) {
+    ABX_HIP(hipEventRecord(b, s));
+    timing_record(name, a, b);
+  }
+  return ABX_OK;
+}
+
+inline unsigned grid_for(int64_t work, int per_block) {
+  int64_t g = (work + per_block - 1) / per_block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// fill kernel (graph-safe replacement for hipMemsetAsync)
+abx_status fill_u32(void *p, uint32_t value, size_t count, hipStream_t s);
+
+// radix sort (sort.hip)
+size_t radix_sort_scratch_bytes(int64_t n, int key_bits);
+abx_status radix_sort(const void *keys_in, const int32_t *vals_in, int64_t n, int key_bits,
+                      void *keys_out, int32_t *vals_out, void *scratch, size_t scratch_bytes,
+                      hipStream_t s);
+
+// exclusive scan of int32 counts into int32 offsets[0..m] (scan.hip);
+// total (int64) is written to *d_total
+size_t scan_scratch_bytes(int64_t m);
+abx_status exclusive_scan(const int32_t *counts, int64_t m, int32_t *offsets, int64_t *d_total,
+                          void *scratch, size_t scratch_bytes, hipStream_t s);
+
+}  // namespace abx
+
+// Opaque handle definition (host memory).
+struct abx_bvh {
+  int64_t n;
+  int32_t kind, format, morton_bits, height;
+  float scene[6];
+  float q_origin[3], q_scale[3];
+  char *tree;  // device base
+  size_t tree_bytes;
+  size_t nodes_off, leaves_off, node_bytes, leaf_bytes;
+  const abx::TreeHeader *hdr() const { return reinterpret_cast<const abx::TreeHeader *>(tree); }
+  const void *nodes() const { return tree + nodes_off; }
+  const void *leaves() const { return tree + leaves_off; }
+};

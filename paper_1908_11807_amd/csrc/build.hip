@@ -1,0 +1,424 @@
+// LBVH construction kernels (ArborX paper, section 2.1):
+//   scene box  -> "Calculate the scene bounding box" (reduction of corners)
+//   Morton     -> "Assign Morton codes for each AABB"
+//   (sort)     -> "Sort the bounding boxes using their Morton code" (sort.hip)
+//   Karras     -> "Generate the bounding volume hierarchy" (Karras 2012)
+//   refit      -> "Calculate internal nodes bounding boxes" (bottom-up, one
+//                 thread per leaf, the second child to arrive continues)
+//   quantise   -> 16-bit node boxes rounded outward (bandwidth reduction the
+//                 paper cites from the literature; not the paper's own step)
+#include <algorithm>
+
+#include "abx_internal.h"
+
+namespace abx {
+
+constexpr int kBuildBlock = 256;
+constexpr int kScenePartials = 1024;
+
+// ------------------------------------------------------------ scene box
+template <int KIND>
+__global__ __launch_bounds__(kBuildBlock) void k_scene_partial(const float *__restrict__ p,
+                                                               int64_t n,
+                                                               float *__restrict__ partial) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float l = KIND == ABX_PRIM_POINTS ? p[3 * i + a] : p[6 * i + a];
+      const float h = KIND == ABX_PRIM_POINTS ? l : p[6 * i + 3 + a];
+      bad |= !__builtin_isfinite(l) || !__builtin_isfinite(h) || !(l <= h);
+      lo[a] = fminf(lo[a], l);
+      hi[a] = fmaxf(hi[a], h);
+    }
+  }
+  __shared__ float s[kBuildBlock / kWave][7];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], __shfl_down(lo[a], o, kWave));
+      hi[a] = fmaxf(hi[a], __shfl_down(hi[a], o, kWave));
+    }
+    bad |= __shfl_down(bad, o, kWave);
+  }
+  if (lane == 0) {
+    for (int a = 0; a < 3; ++a) {
+      s[wave][a] = lo[a];
+      s[wave][3 + a] = hi[a];
+    }
+    s[wave][6] = (float)bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int a = threadIdx.x;
+    float v = s[0][a];
+    for (int w = 1; w < kBuildBlock / kWave; ++w)
+      v = a < 3 ? fminf(v, s[w][a]) : fmaxf(v, s[w][a]);
+    partial[blockIdx.x * 8 + a] = v;
+  }
+}
+
+// One thread per axis (plus one for the flag): final reduction and the Q16
+// grid.  The grid step s is the smallest float with
+// fmaf(65535, s, lo) >= hi, so the top code covers the scene box.
+__global__ void k_scene_final(const float *__restrict__ partial, int blocks,
+                              TreeHeader *__restrict__ hdr) {
+  const int a = threadIdx.x;
+  if (a < 3) {
+    float lo = INFINITY, hi = -INFINITY;
+    for (int b = 0; b < blocks; ++b) {
+      lo = fminf(lo, partial[b * 8 + a]);
+      hi = fmaxf(hi, partial[b * 8 + 3 + a]);
+    }
+    hdr->scene[a] = lo;
+    hdr->scene[3 + a] = hi;
+    const float ext = hi - lo;
+    hdr->inv_ext[a] = ext > 0.0f ? 1.0f / ext : 0.0f;
+    float sc = 0.0f;
+    int overflow = 0;
+    if (ext > 0.0f) {
+      if (!__builtin_isfinite(ext)) {
+        overflow = 1;
+      } else {
+        sc = ext / (float)kQ16Max;
+        while (__fmaf_rn((float)kQ16Max, sc, lo) < hi) sc = nextafterf(sc, INFINITY);
+      }
+    }
+    hdr->q_origin[a] = lo;
+    hdr->q_scale[a] = sc;
+    if (overflow) atomicOr(&hdr->bad, 2);
+  } else if (a == 3) {
+    int bad = 0;
+    for (int b = 0; b < blocks; ++b) bad |= partial[b * 8 + 6] != 0.0f;
+    if (bad) atomicOr(&hdr->bad, 1);
+    hdr->height = 0;
+  }
+}
+
+__global__ void k_header_init(TreeHeader *hdr) {
+  if (threadIdx.x == 0) {
+    hdr->bad = 0;
+    hdr->height = 0;
+  }
+}
+
+// ------------------------------------------------------------ Morton codes
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t spread21(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x001f00000000ffffull;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+// quantised coordinate of c on `bits` bits: scaled by the scene box into
+// [0,1] (float32: inverse extent, clamp), truncated, clamped to 2^bits - 1
+__device__ __forceinline__ uint32_t quantise_axis(float c, float lo, float inv, int bits) {
+  float u = (c - lo) * inv;
+  u = u > 0.0f ? u : 0.0f;
+  u = u > 1.0f ? 1.0f : u;
+  const uint32_t q = (uint32_t)(u * (float)(1u << bits));
+  const uint32_t qmax = (1u << bits) - 1u;
+  return q > qmax ? qmax : q;
+}
+
+template <int KIND, typename K>
+__global__ __launch_bounds__(kBuildBlock) void k_morton(const float *__restrict__ p, int64_t n,
+                                                        const float *__restrict__ scene, int bits,
+                                                        K *__restrict__ codes) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = scene[a];
+    const float ext = scene[3 + a] - lo;
+    const float inv = ext > 0.0f ? 1.0f / ext : 0.0f;
+    const float c = KIND == ABX_PRIM_POINTS ? p[3 * i + a] : 0.5f * (p[6 * i + a] + p[6 * i + 3 + a]);
+    q[a] = quantise_axis(c, lo, inv, bits);
+  }
+  if (bits <= 10)
+    codes[i] = (K)((spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]));
+  else
+    codes[i] = (K)((spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]));
+}
+
+// ------------------------------------------------------------ Karras 2012
+// Common-prefix length of the index-augmented codes at sorted positions i
+// and j (-1 outside [0, n)).  Equal codes fall back to the positions, which
+// makes every augmented code unique (section 2.1: codes "augmented with an
+// index").
+template <typename K>
+__device__ __forceinline__ int delta(const K *__restrict__ keys, int64_t n, int64_t i, K ki,
+                                     int64_t j) {
+  if (j < 0 || j >= n) return -1;
+  const K kj = keys[j];
+  if (ki != kj) return sizeof(K) == 8 ? __clzll((long long)(ki ^ kj)) : __clz((int)(ki ^ kj));
+  return (int)(8 * sizeof(K)) + __clz((int)((uint32_t)i ^ (uint32_t)j));
+}
+
+// One thread per internal node i: direction from the neighbours, range end
+// by exponential then binary search, split by binary search on the prefix,
+// children at gamma / gamma+1 (leaf when the child range has one element).
+// Writes the two child references, the parents (parent<<1 | side) and clears
+// the node's arrival counter.
+template <typename K>
+__global__ __launch_bounds__(kBuildBlock) void k_karras(const K *__restrict__ keys, int64_t n,
+                                                        NodeF32 *__restrict__ nodes,
+                                                        int32_t *__restrict__ parent_leaf,
+                                                        int32_t *__restrict__ parent_int,
+                                                        uint32_t *__restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const K ki = keys[i];
+  const int d = delta(keys, n, i, ki, i + 1) - delta(keys, n, i, ki, i - 1) >= 0 ? 1 : -1;
+  const int dmin = delta(keys, n, i, ki, i - d);
+  int64_t lmax = 2;
+  while (delta(keys, n, i, ki, i + lmax * d) > dmin) lmax <<= 1;
+  int64_t l = 0;
+  for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+    if (delta(keys, n, i, ki, i + (l + t) * d) > dmin) l += t;
+  const int64_t j = i + l * d;
+  const int dnode = delta(keys, n, i, ki, j);
+  int64_t s = 0, t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (delta(keys, n, i, ki, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+  const int64_t first = i < j ? i : j, last = i < j ? j : i;
+  const bool left_leaf = first == gamma, right_leaf = last == gamma + 1;
+  const int32_t lref = left_leaf ? ~(int32_t)gamma : (int32_t)gamma;
+  const int32_t rref = right_leaf ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
+  nodes[i].d = make_int4(lref, rref, 0, 0);
+  const int32_t pl = (int32_t)(i << 1), pr = (int32_t)((i << 1) | 1);
+  if (left_leaf) parent_leaf[gamma] = pl; else parent_int[gamma] = pl;
+  if (right_leaf) parent_leaf[gamma + 1] = pr; else parent_int[gamma + 1] = pr;
+  flags[i] = 0;
+}
+
+// ------------------------------------------------------------ bottom-up refit
+__device__ __forceinline__ void store_child(NodeF32 *node, int side, const float b[6], int h) {
+  float *f = reinterpret_cast<float *>(node);
+  const int o = side * 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) f[o + k] = b[k];
+  reinterpret_cast<int *>(node)[14 + side] = h;
+}
+
+__device__ __forceinline__ void load_child(const NodeF32 *node, int side, float b[6], int &h) {
+  const float *f = reinterpret_cast<const float *>(node);
+  const int o = side * 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) b[k] = f[o + k];
+  h = reinterpret_cast<const int *>(node)[14 + side];
+}
+
+// One thread per leaf (sorted position p).  The thread writes its box into
+// its slot of the parent node, then bumps the parent's arrival counter: the
+// first arrival stops, the second unions both children and climbs.  The
+// counter update is an acquire-release atomic at agent scope, which orders
+// the box stores before it and the sibling-box loads after it across the
+// XCDs' L2 caches.  For Q16 trees the leaf record (exact box + index) is
+// written here too.
+template <int KIND, bool kQ16>
+__global__ __launch_bounds__(kBuildBlock) void k_refit(const float *__restrict__ prims,
+                                                       const int32_t *__restrict__ perm, int64_t n,
+                                                       const int32_t *__restrict__ parent_leaf,
+                                                       const int32_t *__restrict__ parent_int,
+                                                       NodeF32 *nodes, uint32_t *flags,
+                                                       TreeHeader *hdr, void *q16_leaves) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t orig = perm[p];
+  float b[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    b[a] = KIND == ABX_PRIM_POINTS ? prims[3 * (int64_t)orig + a] : prims[6 * (int64_t)orig + a];
+    b[3 + a] = KIND == ABX_PRIM_POINTS ? b[a] : prims[6 * (int64_t)orig + 3 + a];
+  }
+  if (kQ16) {
+    if (KIND == ABX_PRIM_POINTS) {
+      reinterpret_cast<float4 *>(q16_leaves)[p] = make_float4(b[0], b[1], b[2], __int_as_float(orig));
+    } else {
+      float4 *o = reinterpret_cast<float4 *>(q16_leaves) + 2 * p;
+      o[0] = make_float4(b[0], b[1], b[2], b[3]);
+      o[1] = make_float4(b[4], b[5], __int_as_float(orig), 0.0f);
+    }
+  }
+  if (n == 1) return;
+  int h = 0;
+  int32_t pp = parent_leaf[p];
+  // a well-formed tree is climbed in at most `height` steps (< 128); the
+  // bound only guarantees termination, a violation is reported as bad = 4
+  for (int step = 0;; ++step) {
+    if (step >= 256) {
+      atomicOr(&hdr->bad, 4);
+      return;
+    }
+    const int32_t parent = pp >> 1, side = pp & 1;
+    store_child(nodes + parent, side, b, h);
+    const uint32_t old = __hip_atomic_fetch_add(flags + parent, 1u, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0) return;
+    float sb[6];
+    int sh;
+    load_child(nodes + parent, side ^ 1, sb, sh);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      b[a] = fminf(b[a], sb[a]);
+      b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+    }
+    h = (h > sh ? h : sh) + 1;
+    if (parent == 0) {
+      hdr->height = h;
+      return;
+    }
+    pp = parent_int[parent];
+  }
+}
+
+// ------------------------------------------------------------ Q16 nodes
+__device__ __forceinline__ uint32_t q_lo(float x, float o, float s) {
+  if (s == 0.0f) return 0;
+  double e = floor(((double)x - (double)o) / (double)s);
+  uint32_t q = e <= 0.0 ? 0u : (e >= (double)kQ16Max ? (uint32_t)kQ16Max : (uint32_t)e);
+  while (q > 0 && deq(q, s, o) > x) --q;
+  return q;
+}
+
+__device__ __forceinline__ uint32_t q_hi(float x, float o, float s) {
+  if (s == 0.0f) return 0;
+  double e = ceil(((double)x - (double)o) / (double)s);
+  uint32_t q = e <= 0.0 ? 0u : (e >= (double)kQ16Max ? (uint32_t)kQ16Max : (uint32_t)e);
+  while (q < (uint32_t)kQ16Max && deq(q, s, o) < x) ++q;
+  return q;
+}
+
+__global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restrict__ src,
+                                                          int64_t ni,
+                                                          const TreeHeader *__restrict__ hdr,
+                                                          NodeQ16 *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ni) return;
+  const float *f = reinterpret_cast<const float *>(src + i);
+  const int4 d = src[i].d;
+  uint32_t q[12];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float o = hdr->q_origin[a], s = hdr->q_scale[a];
+      q[6 * c + a] = q_lo(f[6 * c + a], o, s);
+      q[6 * c + 3 + a] = q_hi(f[6 * c + 3 + a], o, s);
+    }
+  }
+  NodeQ16 out;
+  out.a = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16),
+                     q[6] | (q[7] << 16));
+  out.b = make_uint4(q[8] | (q[9] << 16), q[10] | (q[11] << 16), (uint32_t)d.x, (uint32_t)d.y);
+  dst[i] = out;
+}
+
+// ------------------------------------------------------------ host launchers
+abx_status launch_scene(int kind, const float *prims, int64_t n, float *partial, int blocks,
+                        TreeHeader *hdr, hipStream_t s) {
+  ABX_TRY(launch("header_init", s, [&] { k_header_init<<<1, 64, 0, s>>>(hdr); }));
+  if (kind == ABX_PRIM_POINTS)
+    ABX_TRY(launch("scene_partial", s, [&] {
+      k_scene_partial<ABX_PRIM_POINTS><<<blocks, kBuildBlock, 0, s>>>(prims, n, partial);
+    }));
+  else
+    ABX_TRY(launch("scene_partial", s, [&] {
+      k_scene_partial<ABX_PRIM_BOXES><<<blocks, kBuildBlock, 0, s>>>(prims, n, partial);
+    }));
+  return launch("scene_final", s, [&] { k_scene_final<<<1, 64, 0, s>>>(partial, blocks, hdr); });
+}
+
+int scene_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kScenePartials, (n + 4095) / 4096));
+}
+
+abx_status launch_morton(int kind, const float *prims, int64_t n, const float *scene, int bits,
+                         void *codes, bool wide, hipStream_t s) {
+  if (n == 0) return ABX_OK;
+  const unsigned g = grid_for(n, kBuildBlock);
+  if (!wide) {
+    uint32_t *c = static_cast<uint32_t *>(codes);
+    if (kind == ABX_PRIM_POINTS)
+      return launch("morton", s, [&] {
+        k_morton<ABX_PRIM_POINTS, uint32_t><<<g, kBuildBlock, 0, s>>>(prims, n, scene, bits, c);
+      });
+    return launch("morton", s, [&] {
+      k_morton<ABX_PRIM_BOXES, uint32_t><<<g, kBuildBlock, 0, s>>>(prims, n, scene, bits, c);
+    });
+  }
+  uint64_t *c = static_cast<uint64_t *>(codes);
+  if (kind == ABX_PRIM_POINTS)
+    return launch("morton", s, [&] {
+      k_morton<ABX_PRIM_POINTS, uint64_t><<<g, kBuildBlock, 0, s>>>(prims, n, scene, bits, c);
+    });
+  return launch("morton", s, [&] {
+    k_morton<ABX_PRIM_BOXES, uint64_t><<<g, kBuildBlock, 0, s>>>(prims, n, scene, bits, c);
+  });
+}
+
+abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
+                         int32_t *parent_leaf, int32_t *parent_int, uint32_t *flags,
+                         hipStream_t s) {
+  if (n < 2) return ABX_OK;
+  const unsigned g = grid_for(n - 1, kBuildBlock);
+  if (wide)
+    return launch("karras", s, [&] {
+      k_karras<uint64_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint64_t *>(keys), n, nodes,
+                                                   parent_leaf, parent_int, flags);
+    });
+  return launch("karras", s, [&] {
+    k_karras<uint32_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint32_t *>(keys), n, nodes,
+                                                 parent_leaf, parent_int, flags);
+  });
+}
+
+abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
+                        const int32_t *parent_leaf, const int32_t *parent_int, NodeF32 *nodes,
+                        uint32_t *flags, TreeHeader *hdr, void *q16_leaves, hipStream_t s) {
+  if (n == 0) return ABX_OK;
+  const unsigned g = grid_for(n, kBuildBlock);
+#define ABX_REFIT(KD, QQ)                                                                       \
+  return launch("refit", s, [&] {                                                              \
+    k_refit<KD, QQ><<<g, kBuildBlock, 0, s>>>(prims, perm, n, parent_leaf, parent_int, nodes,  \
+                                              flags, hdr, q16_leaves);                          \
+  })
+  if (kind == ABX_PRIM_POINTS) {
+    if (q16) ABX_REFIT(ABX_PRIM_POINTS, true);
+    ABX_REFIT(ABX_PRIM_POINTS, false);
+  }
+  if (q16) ABX_REFIT(ABX_PRIM_BOXES, true);
+  ABX_REFIT(ABX_PRIM_BOXES, false);
+#undef ABX_REFIT
+}
+
+abx_status launch_quantise(const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
+                           hipStream_t s) {
+  if (ni <= 0) return ABX_OK;
+  return launch("quantise", s, [&] {
+    k_quantise<<<grid_for(ni, kBuildBlock), kBuildBlock, 0, s>>>(src, ni, hdr, dst);
+  });
+}
+
+}  // namespace abx

@@ -1,0 +1,542 @@
+// Tree traversal kernels (ArborX paper, section 2.2).
+//
+// Batched mode: one lane per query, queries in Morton order so that the 64
+// lanes of a wavefront walk nearly the same nodes (section 2.2 "Query
+// ordering"); the blockIdx -> query-tile map keeps consecutive tiles on one
+// XCD so that they share that XCD's L2.
+//
+// Spatial (section 2.2 "Traversal for spatial queries"): iterative, with a
+// stack of deferred nodes.  A visited node holds both children's boxes; each
+// child passing the predicate is emitted (leaf) or descended into (internal,
+// the second one deferred on the stack).  Count pass and fill pass (2P).
+//
+// Nearest (section 2.2 "Traversal for nearest queries"): the same stack walk
+// where the nearer child is visited first and the farther one deferred with
+// its distance; a node is pruned when its box is strictly farther than the
+// current k-th candidate, which is how the walk stops once the remaining
+// candidates cannot improve the result.  The k best candidates are kept
+// sorted in registers by (squared distance, index).
+//
+// Stack: the first kLdsDepth entries of each lane live in LDS (column per
+// lane, so a wavefront's pushes hit distinct banks); deeper entries spill
+// to the lane's private memory.  Trees deeper than kMaxDepth are refused on
+// the host.
+#include <climits>
+
+#include "abx_internal.h"
+
+namespace abx {
+
+constexpr int kTravBlock = 256;
+constexpr int kMaxDepth = 128;
+constexpr int kLdsDepthSpatial = 16;
+constexpr int kLdsDepthNearest = 16;
+
+struct TreeArgs {
+  const void *nodes;
+  const void *leaves;
+  int64_t n;
+  float scene[6];
+  float qo[3], qs[3];
+};
+
+struct QueryArgs {
+  const float *data;
+  int64_t m;
+  const float *radii;
+  float radius;
+  const int32_t *order;  // sorted position -> caller's query index (or null)
+};
+
+// hardware dispatches workgroup b to XCD b % 8; hand XCD x a contiguous
+// range of tiles so neighbouring (Morton-adjacent) tiles share an L2
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t x = b & 7, k = b >> 3, q = nb >> 3, rem = nb & 7;
+  return x * q + (x < rem ? x : rem) + k;
+}
+
+struct Kids {
+  float l[6], r[6];
+  int32_t lref, rref;
+};
+
+template <int FMT>
+__device__ __forceinline__ void load_kids(const TreeArgs &t, int32_t node, Kids &k) {
+  if (FMT == ABX_NODES_FP32) {
+    const float4 *p = reinterpret_cast<const float4 *>(t.nodes) + 4 * (int64_t)node;
+    const float4 a = p[0], b = p[1], c = p[2];
+    const int4 d = reinterpret_cast<const int4 *>(p)[3];
+    k.l[0] = a.x; k.l[1] = a.y; k.l[2] = a.z; k.l[3] = a.w; k.l[4] = b.x; k.l[5] = b.y;
+    k.r[0] = b.z; k.r[1] = b.w; k.r[2] = c.x; k.r[3] = c.y; k.r[4] = c.z; k.r[5] = c.w;
+    k.lref = d.x;
+    k.rref = d.y;
+  } else {
+    const uint4 *p = reinterpret_cast<const uint4 *>(t.nodes) + 2 * (int64_t)node;
+    const uint4 a = p[0], b = p[1];
+    const uint32_t w[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint32_t q = (w[j / 2] >> (16 * (j & 1))) & 0xffffu;
+      const int ax = j % 3;
+      k.l[j] = deq(q, t.qs[ax], t.qo[ax]);
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint32_t q = (w[3 + j / 2] >> (16 * (j & 1))) & 0xffffu;
+      const int ax = j % 3;
+      k.r[j] = deq(q, t.qs[ax], t.qo[ax]);
+    }
+    k.lref = (int32_t)b.z;
+    k.rref = (int32_t)b.w;
+  }
+}
+
+// exact box of the leaf at sorted position `leaf` (Q16 leaf record) and its
+// primitive's index
+template <int KIND>
+__device__ __forceinline__ int32_t load_leaf_q16(const TreeArgs &t, int32_t leaf, float b[6]) {
+  if (KIND == ABX_PRIM_POINTS) {
+    const float4 v = reinterpret_cast<const float4 *>(t.leaves)[leaf];
+    b[0] = b[3] = v.x;
+    b[1] = b[4] = v.y;
+    b[2] = b[5] = v.z;
+    return __float_as_int(v.w);
+  } else {
+    const float4 *p = reinterpret_cast<const float4 *>(t.leaves) + 2 * (int64_t)leaf;
+    const float4 u = p[0], v = p[1];
+    b[0] = u.x; b[1] = u.y; b[2] = u.z; b[3] = u.w; b[4] = v.x; b[5] = v.y;
+    return __float_as_int(v.z);
+  }
+}
+
+// Per-lane stack: entry e of lane t lives at lds[e * kTravBlock + t] for
+// e < S, else at ovf[e - S] in the lane's private memory.  The LDS part is
+// addressed through an explicit LDS (address space 3) pointer so that the
+// two paths stay separate instructions (the compiler would otherwise merge
+// them into one generic flat access, slower on the common LDS path).
+#define ABX_LDS __attribute__((address_space(3)))
+
+template <typename T, int S>
+__device__ __forceinline__ void stack_push(ABX_LDS T *lds, T *ovf, int &sp, T x) {
+  if (sp < S) {
+    lds[sp * kTravBlock] = x;
+  } else {
+    ovf[sp - S] = x;
+  }
+  ++sp;
+}
+
+template <typename T, int S>
+__device__ __forceinline__ T stack_pop(ABX_LDS T *lds, const T *ovf, int &sp) {
+  --sp;
+  T v;
+  if (sp < S) {
+    v = lds[sp * kTravBlock];
+  } else {
+    v = ovf[sp - S];
+  }
+  return v;
+}
+
+// the nearest traversal's stack holds (node, box distance) pairs
+template <int S>
+__device__ __forceinline__ void stack_push2(ABX_LDS int32_t *ln, ABX_LDS float *ld, int32_t *on,
+                                            float *od, int &sp, int32_t n, float d) {
+  if (sp < S) {
+    ln[sp * kTravBlock] = n;
+    ld[sp * kTravBlock] = d;
+  } else {
+    on[sp - S] = n;
+    od[sp - S] = d;
+  }
+  ++sp;
+}
+
+template <int S>
+__device__ __forceinline__ void stack_pop2(ABX_LDS int32_t *ln, ABX_LDS float *ld, const int32_t *on,
+                                           const float *od, int &sp, int32_t &n, float &d) {
+  --sp;
+  if (sp < S) {
+    n = ln[sp * kTravBlock];
+    d = ld[sp * kTravBlock];
+  } else {
+    n = on[sp - S];
+    d = od[sp - S];
+  }
+}
+
+enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_STATS = 2 };
+
+// ------------------------------------------------------------------ spatial
+template <int PRED>
+struct SpatialQuery {
+  float a[3], b[3];  // WITHIN: a = point, b[0] = r^2 ; INTERSECTS: a = lo, b = hi
+  __device__ __forceinline__ bool test(const float *x) const {
+    if (PRED == ABX_PRED_WITHIN)
+      return box_dist2(x[0], x[1], x[2], x[3], x[4], x[5], a[0], a[1], a[2]) <= b[0];
+    return box_overlap(x[0], x[1], x[2], x[3], x[4], x[5], a[0], a[1], a[2], b[0], b[1], b[2]);
+  }
+};
+
+template <int KIND, int PRED, int FMT, int MODE>
+__global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa,
+                                                        int32_t *__restrict__ out_counts,
+                                                        const int32_t *__restrict__ offsets,
+                                                        int32_t *__restrict__ indices) {
+  __shared__ int32_t s_stack[kLdsDepthSpatial * kTravBlock];
+  const int64_t tq = xcd_tile(blockIdx.x, gridDim.x) * kTravBlock + threadIdx.x;
+  if (tq >= qa.m) return;
+  const int64_t qi = qa.order ? qa.order[tq] : tq;
+  SpatialQuery<PRED> q;
+  if (PRED == ABX_PRED_WITHIN) {
+    const float *p = qa.data + 3 * qi;
+    q.a[0] = p[0]; q.a[1] = p[1]; q.a[2] = p[2];
+    const float r = qa.radii ? qa.radii[qi] : qa.radius;
+    q.b[0] = r >= 0.0f ? r * r : -1.0f;
+    q.b[1] = q.b[2] = 0.0f;
+  } else {
+    const float *p = qa.data + 6 * qi;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      q.a[a] = p[a];
+      q.b[a] = p[3 + a];
+    }
+  }
+  int32_t *out = MODE == MODE_FILL ? indices + offsets[qi] : nullptr;
+  const int32_t row_len = MODE == MODE_FILL ? offsets[qi + 1] - offsets[qi] : 0;
+  const int32_t *perm = reinterpret_cast<const int32_t *>(t.leaves);
+  int32_t cnt = 0, visited = 0, leaf_reads = 0;
+
+  // a leaf child whose (node-stored) box passed: confirm and emit
+  auto leaf = [&](int32_t pos, const float *box) {
+    if (FMT == ABX_NODES_FP32) {
+      if (MODE == MODE_FILL && cnt < row_len) out[cnt] = perm[pos];
+      ++cnt;
+      if (MODE == MODE_STATS) ++leaf_reads;
+    } else {
+      float b[6];
+      const int32_t idx = load_leaf_q16<KIND>(t, pos, b);
+      if (MODE == MODE_STATS) ++leaf_reads;
+      if (q.test(b)) {
+        if (MODE == MODE_FILL && cnt < row_len) out[cnt] = idx;
+        ++cnt;
+      }
+    }
+    (void)box;
+  };
+
+  if (t.n == 1) {
+    if (FMT == ABX_NODES_FP32) {
+      if (q.test(t.scene)) leaf(0, t.scene);
+    } else {
+      leaf(0, t.scene);
+    }
+  } else {
+    int32_t ovf[kMaxDepth - kLdsDepthSpatial];
+    ABX_LDS int32_t *lds = (ABX_LDS int32_t *)(s_stack) + threadIdx.x;
+    int sp = 0;
+    int32_t node = 0;
+    // a tree has n-1 internal nodes, each visited at most once: the bound
+    // only guarantees termination
+    for (int64_t it = 0; it < t.n; ++it) {
+      Kids k;
+      load_kids<FMT>(t, node, k);
+      if (MODE == MODE_STATS) ++visited;
+      const bool hl = q.test(k.l), hr = q.test(k.r);
+      const bool ll = k.lref < 0, lr = k.rref < 0;
+      if (hl && ll) leaf(~k.lref, k.l);
+      if (hr && lr) leaf(~k.rref, k.r);
+      const bool gl = hl && !ll, gr = hr && !lr;
+      if (gl) {
+        if (gr && sp < kMaxDepth) stack_push<int32_t, kLdsDepthSpatial>(lds, ovf, sp, k.rref);
+        node = k.lref;
+      } else if (gr) {
+        node = k.rref;
+      } else {
+        if (sp == 0) break;
+        node = stack_pop<int32_t, kLdsDepthSpatial>(lds, ovf, sp);
+      }
+    }
+  }
+  if (MODE == MODE_COUNT) out_counts[qi] = cnt;
+  if (MODE == MODE_STATS) {
+    out_counts[2 * qi] = visited;
+    out_counts[2 * qi + 1] = leaf_reads;
+  }
+}
+
+// ------------------------------------------------------------------ nearest
+// (d, i) precedes (e, j) in (distance, index) order
+__device__ __forceinline__ bool precedes(float d, int32_t i, float e, int32_t j) {
+  return d < e || (d == e && i < j);
+}
+
+// Insert (d, idx) -- known to precede the last entry -- into the ascending
+// register list, dropping the last entry.  Fully unrolled: constant register
+// indices only.
+template <int K>
+__device__ __forceinline__ void knn_insert(float (&bd)[K], int32_t (&bi)[K], float d, int32_t idx) {
+  bool after_prev = true;  // x precedes a[j] (true for j = K-1)
+#pragma unroll
+  for (int j = K - 1; j > 0; --j) {
+    const bool lt_prev = precedes(d, idx, bd[j - 1], bi[j - 1]);
+    const float nd = lt_prev ? bd[j - 1] : (after_prev ? d : bd[j]);
+    const int32_t ni = lt_prev ? bi[j - 1] : (after_prev ? idx : bi[j]);
+    bd[j] = nd;
+    bi[j] = ni;
+    after_prev = lt_prev;
+  }
+  if (after_prev) {
+    bd[0] = d;
+    bi[0] = idx;
+  }
+}
+
+template <int KIND, int FMT, int K, bool STATS>
+__global__ __launch_bounds__(kTravBlock) void k_nearest(TreeArgs t, const float *__restrict__ pts,
+                                                        int64_t m, const int32_t *__restrict__ order,
+                                                        int k, int32_t *__restrict__ indices,
+                                                        float *__restrict__ dist,
+                                                        int32_t *__restrict__ stats) {
+  __shared__ int32_t s_node[kLdsDepthNearest * kTravBlock];
+  __shared__ float s_dist[kLdsDepthNearest * kTravBlock];
+  const int64_t tq = xcd_tile(blockIdx.x, gridDim.x) * kTravBlock + threadIdx.x;
+  if (tq >= m) return;
+  const int64_t qi = order ? order[tq] : tq;
+  const float qx = pts[3 * qi], qy = pts[3 * qi + 1], qz = pts[3 * qi + 2];
+  const int32_t *perm = reinterpret_cast<const int32_t *>(t.leaves);
+
+  // slots [0, K-k) hold sentinels that precede everything and never move;
+  // the k live slots start empty (+inf)
+  float bd[K];
+  int32_t bi[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const bool dummy = j < K - k;
+    bd[j] = dummy ? -1.0f : INFINITY;
+    bi[j] = dummy ? -1 : INT_MAX;
+  }
+  int32_t visited = 0, leaf_reads = 0;
+
+  auto consider_leaf = [&](int32_t pos, float dbox) {
+    if (FMT == ABX_NODES_FP32) {
+      // the node box of a leaf child is the primitive's exact box
+      if (dbox <= bd[K - 1]) {
+        const int32_t idx = perm[pos];
+        if (STATS) ++leaf_reads;
+        if (precedes(dbox, idx, bd[K - 1], bi[K - 1])) knn_insert<K>(bd, bi, dbox, idx);
+      }
+    } else {
+      if (dbox <= bd[K - 1]) {
+        float b[6];
+        const int32_t idx = load_leaf_q16<KIND>(t, pos, b);
+        if (STATS) ++leaf_reads;
+        const float d = box_dist2(b[0], b[1], b[2], b[3], b[4], b[5], qx, qy, qz);
+        if (precedes(d, idx, bd[K - 1], bi[K - 1])) knn_insert<K>(bd, bi, d, idx);
+      }
+    }
+  };
+
+  if (t.n == 1) {
+    const float d = box_dist2(t.scene[0], t.scene[1], t.scene[2], t.scene[3], t.scene[4],
+                              t.scene[5], qx, qy, qz);
+    consider_leaf(0, d);
+  } else {
+    int32_t ovf_n[kMaxDepth - kLdsDepthNearest];
+    float ovf_d[kMaxDepth - kLdsDepthNearest];
+    ABX_LDS int32_t *lds_n = (ABX_LDS int32_t *)(s_node) + threadIdx.x;
+    ABX_LDS float *lds_d = (ABX_LDS float *)(s_dist) + threadIdx.x;
+    int sp = 0;
+    int32_t node = 0;
+    for (int64_t it = 0; it < t.n; ++it) {
+      Kids c;
+      load_kids<FMT>(t, node, c);
+      if (STATS) ++visited;
+      const float dl = box_dist2(c.l[0], c.l[1], c.l[2], c.l[3], c.l[4], c.l[5], qx, qy, qz);
+      const float dr = box_dist2(c.r[0], c.r[1], c.r[2], c.r[3], c.r[4], c.r[5], qx, qy, qz);
+      const bool ll = c.lref < 0, lr = c.rref < 0;
+      if (ll) consider_leaf(~c.lref, dl);
+      if (lr) consider_leaf(~c.rref, dr);
+      const float kth = bd[K - 1];
+      const bool gl = !ll && dl <= kth, gr = !lr && dr <= kth;
+      if (gl && gr) {
+        const bool left_first = dl <= dr;
+        if (sp < kMaxDepth)
+          stack_push2<kLdsDepthNearest>(lds_n, lds_d, ovf_n, ovf_d, sp, left_first ? c.rref : c.lref,
+                                        left_first ? dr : dl);
+        node = left_first ? c.lref : c.rref;
+      } else if (gl) {
+        node = c.lref;
+      } else if (gr) {
+        node = c.rref;
+      } else {
+        bool found = false;
+        while (sp > 0) {
+          int32_t en;
+          float ed;
+          stack_pop2<kLdsDepthNearest>(lds_n, lds_d, ovf_n, ovf_d, sp, en, ed);
+          if (ed <= bd[K - 1]) {
+            node = en;
+            found = true;
+            break;
+          }
+        }
+        if (!found) break;
+      }
+    }
+  }
+  if (STATS) {
+    stats[2 * qi] = visited;
+    stats[2 * qi + 1] = leaf_reads;
+    return;
+  }
+  int32_t *oi = indices + qi * k;
+  float *od = dist + qi * k;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if (j >= K - k) {
+      oi[j - (K - k)] = bi[j];
+      od[j - (K - k)] = sqrtf(bd[j]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ query codes
+// 30-bit Morton code of each query's centroid against the tree's scene box
+// (clamped), for the query ordering of section 2.2.
+__device__ __forceinline__ uint32_t spread10q(uint32_t x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+template <int W>
+__global__ __launch_bounds__(kTravBlock) void k_query_codes(const float *__restrict__ q, int64_t m,
+                                                            TreeArgs t, uint32_t *__restrict__ codes) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint32_t c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = W == 3 ? q[3 * i + a] : 0.5f * (q[6 * i + a] + q[6 * i + 3 + a]);
+    const float lo = t.scene[a], ext = t.scene[3 + a] - lo;
+    const float inv = ext > 0.0f ? 1.0f / ext : 0.0f;
+    float u = (x - lo) * inv;
+    u = u > 0.0f ? u : 0.0f;
+    u = u < 1.0f ? u : 1.0f;
+    const uint32_t v = (uint32_t)(u * 1024.0f);
+    c[a] = v > 1023u ? 1023u : v;
+  }
+  codes[i] = (spread10q(c[0]) << 2) | (spread10q(c[1]) << 1) | spread10q(c[2]);
+}
+
+// ------------------------------------------------------------ host launchers
+TreeArgs tree_args(const abx_bvh *b) {
+  TreeArgs t;
+  t.nodes = b->nodes();
+  t.leaves = b->leaves();
+  t.n = b->n;
+  for (int a = 0; a < 6; ++a) t.scene[a] = b->scene[a];
+  for (int a = 0; a < 3; ++a) {
+    t.qo[a] = b->q_origin[a];
+    t.qs[a] = b->q_scale[a];
+  }
+  return t;
+}
+
+abx_status launch_query_codes(const abx_bvh *b, const float *q, int64_t m, int width,
+                              uint32_t *codes, hipStream_t s) {
+  if (m == 0) return ABX_OK;
+  const TreeArgs t = tree_args(b);
+  const unsigned g = grid_for(m, kTravBlock);
+  if (width == 3)
+    return launch("query_codes", s, [&] { k_query_codes<3><<<g, kTravBlock, 0, s>>>(q, m, t, codes); });
+  return launch("query_codes", s, [&] { k_query_codes<6><<<g, kTravBlock, 0, s>>>(q, m, t, codes); });
+}
+
+template <int KIND, int PRED, int FMT>
+abx_status spatial_fmt(const abx_bvh *b, const QueryArgs &qa, int mode, int32_t *counts,
+                       const int32_t *offsets, int32_t *indices, hipStream_t s) {
+  const TreeArgs t = tree_args(b);
+  const unsigned g = grid_for(qa.m, kTravBlock);
+  const char *name = mode == MODE_COUNT ? "spatial_count" : mode == MODE_FILL ? "spatial_fill"
+                                                                              : "spatial_stats";
+  return launch(name, s, [&] {
+    if (mode == MODE_COUNT)
+      k_spatial<KIND, PRED, FMT, MODE_COUNT><<<g, kTravBlock, 0, s>>>(t, qa, counts, offsets, indices);
+    else if (mode == MODE_FILL)
+      k_spatial<KIND, PRED, FMT, MODE_FILL><<<g, kTravBlock, 0, s>>>(t, qa, counts, offsets, indices);
+    else
+      k_spatial<KIND, PRED, FMT, MODE_STATS><<<g, kTravBlock, 0, s>>>(t, qa, counts, offsets, indices);
+  });
+}
+
+template <int KIND, int PRED>
+abx_status spatial_pred(const abx_bvh *b, const QueryArgs &qa, int mode, int32_t *counts,
+                        const int32_t *offsets, int32_t *indices, hipStream_t s) {
+  if (b->format == ABX_NODES_FP32)
+    return spatial_fmt<KIND, PRED, ABX_NODES_FP32>(b, qa, mode, counts, offsets, indices, s);
+  return spatial_fmt<KIND, PRED, ABX_NODES_Q16>(b, qa, mode, counts, offsets, indices, s);
+}
+
+abx_status launch_spatial(const abx_bvh *b, int pred, const float *data, int64_t m,
+                          const float *radii, float radius, const int32_t *order, int mode,
+                          int32_t *counts, const int32_t *offsets, int32_t *indices, hipStream_t s) {
+  if (m == 0) return ABX_OK;
+  QueryArgs qa{data, m, radii, radius, order};
+  if (b->kind == ABX_PRIM_POINTS) {
+    if (pred == ABX_PRED_WITHIN)
+      return spatial_pred<ABX_PRIM_POINTS, ABX_PRED_WITHIN>(b, qa, mode, counts, offsets, indices, s);
+    return spatial_pred<ABX_PRIM_POINTS, ABX_PRED_INTERSECTS_BOX>(b, qa, mode, counts, offsets, indices, s);
+  }
+  if (pred == ABX_PRED_WITHIN)
+    return spatial_pred<ABX_PRIM_BOXES, ABX_PRED_WITHIN>(b, qa, mode, counts, offsets, indices, s);
+  return spatial_pred<ABX_PRIM_BOXES, ABX_PRED_INTERSECTS_BOX>(b, qa, mode, counts, offsets, indices, s);
+}
+
+template <int KIND, int FMT, int K>
+abx_status nearest_k(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order, int k,
+                     int32_t *idx, float *dist, int32_t *stats, hipStream_t s) {
+  const TreeArgs t = tree_args(b);
+  const unsigned g = grid_for(m, kTravBlock);
+  if (stats)
+    return launch("nearest_stats", s, [&] {
+      k_nearest<KIND, FMT, K, true><<<g, kTravBlock, 0, s>>>(t, pts, m, order, k, idx, dist, stats);
+    });
+  return launch("nearest", s, [&] {
+    k_nearest<KIND, FMT, K, false><<<g, kTravBlock, 0, s>>>(t, pts, m, order, k, idx, dist, stats);
+  });
+}
+
+template <int KIND, int FMT>
+abx_status nearest_fmt(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order, int k,
+                       int32_t *idx, float *dist, int32_t *stats, hipStream_t s) {
+  if (k <= 1) return nearest_k<KIND, FMT, 1>(b, pts, m, order, k, idx, dist, stats, s);
+  if (k <= 2) return nearest_k<KIND, FMT, 2>(b, pts, m, order, k, idx, dist, stats, s);
+  if (k <= 4) return nearest_k<KIND, FMT, 4>(b, pts, m, order, k, idx, dist, stats, s);
+  if (k <= 8) return nearest_k<KIND, FMT, 8>(b, pts, m, order, k, idx, dist, stats, s);
+  if (k <= 10) return nearest_k<KIND, FMT, 10>(b, pts, m, order, k, idx, dist, stats, s);
+  if (k <= 16) return nearest_k<KIND, FMT, 16>(b, pts, m, order, k, idx, dist, stats, s);
+  return nearest_k<KIND, FMT, 32>(b, pts, m, order, k, idx, dist, stats, s);
+}
+
+abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order,
+                          int k, int32_t *idx, float *dist, int32_t *stats, hipStream_t s) {
+  if (m == 0 || k == 0) return ABX_OK;
+  if (k > 32) return ABX_ERR_UNSUPPORTED;
+  if (b->kind == ABX_PRIM_POINTS) {
+    if (b->format == ABX_NODES_FP32)
+      return nearest_fmt<ABX_PRIM_POINTS, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, s);
+    return nearest_fmt<ABX_PRIM_POINTS, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, s);
+  }
+  if (b->format == ABX_NODES_FP32)
+    return nearest_fmt<ABX_PRIM_BOXES, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, s);
+  return nearest_fmt<ABX_PRIM_BOXES, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, s);
+}
+
+int max_tree_depth() { return kMaxDepth; }
+
+}  // namespace abx

@@ -1,0 +1,166 @@
+"""Comparison rules between the HIP path and the CPU oracle.
+
+Spatial (within): per query, the GPU index set equals the oracle's except
+for pairs whose double-precision distance lies within 1e-6 relative of the
+radius; those are exempt and counted.  Box intersection: exactly equal.
+
+Nearest: row length min(k, n); GPU indices distinct and valid; the sorted
+double-precision distances of the GPU's indices match the oracle's, element
+by element, within 1e-6 relative; index sets equal except indices whose
+distance is within 1e-6 relative of the oracle's k-th distance (exempt and
+counted); each GPU float distance is within 1e-6 relative of the recomputed
+double distance.
+"""
+import numpy as np
+
+REL = 1e-6
+
+
+def _rel_close(a, b, rel=REL):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.abs(a - b) <= rel * np.maximum(np.abs(a), np.abs(b))
+
+
+def check_spatial(orc, prims, kind, queries, pred, gpu_off, gpu_idx, radius=0.0, radii=None,
+                  rows=None):
+    """Compare GPU CSR rows (all, or the sampled `rows`) with the oracle.
+    Returns the number of exempt boundary pairs."""
+    gpu_off = np.asarray(gpu_off, np.int64)
+    gpu_idx = np.asarray(gpu_idx, np.int64)
+    qw = 3 if pred == orc.WITHIN else 6
+    q = np.asarray(queries, np.float32).reshape(-1, qw)
+    m = q.shape[0]
+    assert gpu_off.shape == (m + 1,)
+    assert gpu_off[0] == 0 and np.all(np.diff(gpu_off) >= 0) and gpu_off[-1] == gpu_idx.shape[0]
+    sel = np.arange(m) if rows is None else np.asarray(rows)
+    rr = None if radii is None else np.asarray(radii, np.float32)[sel]
+    off, idx = orc.spatial(prims, kind, q[sel], pred, radius=radius, radii=rr)
+    exempt = 0
+    n = np.asarray(prims).reshape(-1, 3 if kind == orc.POINTS else 6).shape[0]
+    for t, j in enumerate(sel):
+        g = gpu_idx[gpu_off[j]:gpu_off[j + 1]]
+        assert np.all((g >= 0) & (g < n)), f"row {j}: index out of range"
+        gs = set(g.tolist())
+        assert len(gs) == len(g), f"row {j}: duplicate indices"
+        os_ = set(idx[off[t]:off[t + 1]].tolist())
+        if gs == os_:
+            continue
+        assert pred == orc.WITHIN, f"row {j}: box-intersection sets differ"
+        r = float(np.float32(radius if radii is None else rr[t]))
+        diff = np.array(sorted(gs ^ os_), np.int64)
+        d = orc.distances(prims, kind, q[j], diff)
+        bad = diff[~(np.abs(d - r) <= REL * r)]
+        assert bad.size == 0, f"row {j}: {bad.size} non-boundary mismatches, e.g. {bad[:5]}"
+        exempt += diff.size
+    return exempt
+
+
+def check_nearest(orc, prims, kind, queries, k, gpu_idx, gpu_dist, rows=None):
+    """Returns the number of exempt tie indices."""
+    q = np.asarray(queries, np.float32).reshape(-1, 3)
+    n = np.asarray(prims).reshape(-1, 3 if kind == orc.POINTS else 6).shape[0]
+    kk = min(k, n)
+    gpu_idx = np.asarray(gpu_idx, np.int64)
+    gpu_dist = np.asarray(gpu_dist, np.float64)
+    m = q.shape[0]
+    assert gpu_idx.shape == (m, kk) and gpu_dist.shape == (m, kk)
+    sel = np.arange(m) if rows is None else np.asarray(rows)
+    oi, od = orc.nearest(prims, kind, q[sel], k)
+    exempt = 0
+    for t, j in enumerate(sel):
+        g = gpu_idx[j]
+        assert np.all((g >= 0) & (g < n)), f"row {j}: invalid index"
+        assert len(set(g.tolist())) == kk, f"row {j}: duplicate index"
+        d64 = orc.distances(prims, kind, q[j], g)
+        # rule 5: reported float distance vs recomputed double distance
+        assert np.all(_rel_close(gpu_dist[j], d64) | ((gpu_dist[j] == 0) & (d64 == 0))), \
+            f"row {j}: reported distance off"
+        # rule 3: sorted distances match the oracle's element by element
+        ds = np.sort(d64)
+        assert np.all(_rel_close(ds, od[t]) | ((ds == 0) & (od[t] == 0))), f"row {j}: distances differ"
+        # rule 4: index sets equal up to ties at the k-th distance
+        gs, os_ = set(g.tolist()), set(oi[t].tolist())
+        if gs != os_ and kk > 0:
+            dk = od[t][-1]
+            diff = np.array(sorted(gs ^ os_), np.int64)
+            dd = orc.distances(prims, kind, q[j], diff)
+            bad = diff[~(np.abs(dd - dk) <= REL * max(dk, 1e-300))]
+            assert bad.size == 0, f"row {j}: non-tie index mismatch {bad[:5]}"
+            exempt += diff.size
+        # rows come sorted by (distance, index): non-decreasing float distances
+        assert np.all(np.diff(gpu_dist[j]) >= 0), f"row {j}: not ascending"
+    return exempt
+
+
+# ---------------------------------------------------------------- trees
+def decode_tree(bvh):
+    """Child kinds/indices, permutation, node boxes and (for Q16) exact leaf
+    boxes of a built tree, read back from device memory."""
+    lay = bvh.layout
+    n = bvh.n
+    ni = max(n - 1, 0)
+    nodes = bvh.nodes_bytes().cpu().numpy()
+    leaves = bvh.leaves_bytes().cpu().numpy()
+    out = {}
+    if lay.node_format == 0:
+        f = nodes.view(np.float32).reshape(ni, 16)
+        refs = nodes.view(np.int32).reshape(ni, 16)[:, 12:14]
+        out["boxes_l"] = f[:, 0:6].copy()
+        out["boxes_r"] = f[:, 6:12].copy()
+        out["perm"] = leaves.view(np.int32).astype(np.int64)
+    else:
+        u = nodes.view(np.uint16).reshape(ni, 16)
+        refs = nodes.view(np.int32).reshape(ni, 8)[:, 6:8]
+        out["q_l"] = u[:, 0:6].astype(np.uint32)
+        out["q_r"] = u[:, 6:12].astype(np.uint32)
+        if bvh.kind == 0:
+            lf = leaves.view(np.float32).reshape(n, 4)
+            out["perm"] = leaves.view(np.int32).reshape(n, 4)[:, 3].astype(np.int64)
+            out["leaf_boxes"] = np.concatenate([lf[:, :3], lf[:, :3]], axis=1)
+        else:
+            lf = leaves.view(np.float32).reshape(n, 8)
+            out["perm"] = leaves.view(np.int32).reshape(n, 8)[:, 6].astype(np.int64)
+            out["leaf_boxes"] = lf[:, :6].copy()
+    refs = refs.astype(np.int64)
+    out["child_kind"] = (refs >= 0).astype(np.int8)
+    out["child_index"] = np.where(refs >= 0, refs, ~refs)
+    return out
+
+
+def fmaf32(q, scale, origin):
+    """float32 fmaf(q, scale, origin), correctly rounded, vectorised.
+
+    q * scale is exact in float64 (16-bit by 24-bit significands); adding
+    origin in float64 rounds once more, which can only change the final
+    float32 rounding when the float64 sum lands exactly on a float32
+    midpoint -- those rare cases are redone with exact rationals."""
+    from fractions import Fraction
+    q = np.asarray(q, np.float64)
+    s = np.float64(np.float32(scale))
+    o = np.float64(np.float32(origin))
+    v = q * s + o
+    f = v.astype(np.float32)
+    lo = np.nextafter(f, np.float32(-np.inf))
+    hi = np.nextafter(f, np.float32(np.inf))
+    mid = (v == (f.astype(np.float64) + lo.astype(np.float64)) / 2) | \
+          (v == (f.astype(np.float64) + hi.astype(np.float64)) / 2)
+    for i in zip(*np.nonzero(mid)):
+        exact = Fraction(float(q[i])) * Fraction(float(s)) + Fraction(float(o))
+        cands = [f[i], lo[i], hi[i]]
+        err = [abs(Fraction(float(c)) - exact) for c in cands]
+        best = min(err)
+        pick = [c for c, e in zip(cands, err) if e == best]
+        if len(pick) > 1:   # tie: even significand
+            pick = [c for c in pick if (np.array(c, np.float32).view(np.uint32) & 1) == 0]
+        f[i] = pick[0]
+    return f
+
+
+def dequantise(qbox, origin, scale):
+    """Dequantised [.., 6] boxes, per the traversal's fmaf(q, scale, origin)."""
+    out = np.empty(qbox.shape, np.float32)
+    for c in range(6):
+        a = c % 3
+        out[..., c] = fmaf32(qbox[..., c], scale[a], origin[a])
+    return out

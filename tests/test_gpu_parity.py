@@ -1,0 +1,309 @@
+"""GPU parity: every kernel and every entry point of libabx against the CPU
+oracle, on seeded inputs that span several tiles and a ragged tail, plus the
+edge cases of the method.  Runs only on an MI355X (marker `gpu`)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1908_11807_amd import abx, datagen
+from parity import check_nearest, check_spatial, decode_tree, dequantise
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ----------------------------------------------------------- building blocks
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("bits", [10, 21])
+def test_morton_codes_bit_exact(orc, kind, bits):
+    pts = datagen.clusters(20_011, 3)
+    prims = pts if kind == 0 else datagen.boxes_around(pts, 4, 0.01)
+    scene, _ = orc.scene_box(prims, kind)
+    want = orc.morton(prims, kind, scene, bits)
+    got = host(abx.morton_codes(dev(prims), dev(scene), bits, kind=kind)).view(np.uint64)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 100_003])
+@pytest.mark.parametrize("key_bits", [30, 63])
+def test_radix_sort_stable(n, key_bits):
+    rng = np.random.default_rng(n + key_bits)
+    # few distinct keys so that stability is exercised
+    keys = rng.integers(0, 2 ** 12, size=n).astype(np.uint64) << np.uint64(key_bits - 12)
+    keys |= rng.integers(0, 3, size=n).astype(np.uint64)
+    if key_bits <= 32:
+        k = dev(keys.astype(np.uint32).view(np.int32))
+    else:
+        k = dev(keys.view(np.int64))
+    ko, vo = abx.radix_sort_pairs(k, key_bits)
+    perm = np.argsort(keys, kind="stable")
+    assert np.array_equal(host(vo), perm)
+    got_keys = host(ko).view(np.uint32 if key_bits <= 32 else np.uint64).astype(np.uint64)
+    assert np.array_equal(got_keys, keys[perm])
+
+
+def test_radix_sort_with_values():
+    rng = np.random.default_rng(5)
+    n = 50_000
+    keys = rng.integers(0, 2 ** 30, size=n).astype(np.uint32)
+    vals = rng.integers(-1000, 1000, size=n).astype(np.int32)
+    ko, vo = abx.radix_sort_pairs(dev(keys.view(np.int32)), 30, vals=dev(vals))
+    perm = np.argsort(keys, kind="stable")
+    assert np.array_equal(host(vo), vals[perm])
+
+
+# ---------------------------------------------------------------- construction
+
+def _check_tree_vs_oracle(orc, prims, kind, bits, fmt):
+    t = abx.bvh_build(dev(prims), kind=kind, node_format=fmt, morton_bits=bits)
+    ref = orc.build(prims, kind, bits)
+    n = prims.shape[0]
+    got = decode_tree(t)
+    assert np.array_equal(got["perm"], ref["perm"])
+    np.testing.assert_array_equal(np.array(t.scene, np.float32), ref["scene"])
+    if n >= 2:
+        assert np.array_equal(got["child_kind"], ref["child_kind"])
+        assert np.array_equal(got["child_index"], ref["child_index"])
+    # node boxes: exact unions (FP32) / outward containment (Q16)
+    ni = max(n - 1, 0)
+    if ni:
+        child_box = np.empty((ni, 2, 6), np.float32)
+        ck, ci = ref["child_kind"], ref["child_index"]
+        sp = np.asarray(prims, np.float32).reshape(n, -1)[ref["perm"]]
+        leafbox = np.concatenate([sp[:, :3], sp[:, :3]], axis=1) if kind == 0 else sp
+        for s in range(2):
+            child_box[:, s] = np.where((ck[:, s] == 0)[:, None], leafbox[np.where(ck[:, s] == 0, ci[:, s], 0)],
+                                       ref["boxes"][np.where(ck[:, s] == 1, ci[:, s], 0)])
+        if fmt == "fp32":
+            np.testing.assert_array_equal(got["boxes_l"], child_box[:, 0])
+            np.testing.assert_array_equal(got["boxes_r"], child_box[:, 1])
+        else:
+            lay = t.layout
+            for s, key in ((0, "q_l"), (1, "q_r")):
+                d = dequantise(got[key], list(lay.q16_origin), list(lay.q16_scale))
+                assert np.all(d[:, :3] <= child_box[:, s, :3]), "q16 lower corner not outward"
+                assert np.all(d[:, 3:] >= child_box[:, s, 3:]), "q16 upper corner not outward"
+    if fmt == "q16":
+        sp = np.asarray(prims, np.float32).reshape(n, -1)[ref["perm"]]
+        leafbox = np.concatenate([sp[:, :3], sp[:, :3]], axis=1) if kind == 0 else sp
+        np.testing.assert_array_equal(got["leaf_boxes"], leafbox)
+    return t
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 1000, 4097, 10_000])
+@pytest.mark.parametrize("bits", [10, 21])
+def test_build_points_matches_oracle(orc, n, bits):
+    _check_tree_vs_oracle(orc, datagen.uniform_cube(n, 100 + n), 0, bits, "fp32")
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_build_formats_and_kinds(orc, fmt, kind):
+    pts = datagen.clusters(12_345, 9)
+    prims = pts if kind == 0 else datagen.boxes_around(pts, 10, 0.003)
+    _check_tree_vs_oracle(orc, prims, kind, 21, fmt)
+
+
+def test_build_duplicates_and_degenerate_axis(orc):
+    rng = np.random.default_rng(1)
+    pts = rng.integers(0, 4, size=(3000, 3)).astype(np.float32)   # heavy duplicates
+    pts[:, 2] = 0.5                                                # zero-extent axis
+    for bits in (10, 21):
+        for fmt in ("fp32", "q16"):
+            _check_tree_vs_oracle(orc, pts, 0, bits, fmt)
+
+
+def test_build_fig1(orc):
+    leaves = np.array([[0.9, 0.25, 0, 1.04, 0.43, 0], [0.16, 0.2, 0, 0.30, 0.38, 0],
+                       [0.6, 0.9, 0, 0.74, 1.08, 0], [0.2, 0.7, 0, 0.34, 0.88, 0],
+                       [0.7, 0.2, 0, 0.84, 0.38, 0], [0, 0.1, 0, 0.14, 0.28, 0],
+                       [0.5, 0.4, 0, 0.64, 0.58, 0], [0.8, 0.7, 0, 0.94, 0.88, 0]], np.float32)
+    for bits in (10, 21):
+        _check_tree_vs_oracle(orc, leaves, 1, bits, "fp32")
+
+
+def test_build_rejects_nan_and_inverted(orc):
+    p = datagen.uniform_cube(100, 1)
+    p[50, 1] = np.nan
+    with pytest.raises(abx.AbxError) as e:
+        abx.bvh_build(dev(p))
+    assert e.value.status == abx.ERR_INVALID_INPUT
+    b = datagen.boxes_around(datagen.uniform_cube(100, 2), 3, 0.1)
+    b[7, 0], b[7, 3] = b[7, 3], b[7, 0] - 1
+    with pytest.raises(abx.AbxError) as e:
+        abx.bvh_build(dev(b), kind=1)
+    assert e.value.status == abx.ERR_INVALID_INPUT
+
+
+def test_build_height_bound(orc):
+    t = abx.bvh_build(dev(datagen.uniform_cube(10_000, 3)))
+    ref = orc.build(datagen.uniform_cube(10_000, 3), 0, 21)
+    # height = longest root-to-leaf path of the oracle's tree
+    ck, ci = ref["child_kind"], ref["child_index"]
+    depth = {0: 0}
+    best = 0
+    stack = [0]
+    while stack:
+        i = stack.pop()
+        for s in range(2):
+            if ck[i, s] == 1:
+                depth[ci[i, s]] = depth[i] + 1
+                stack.append(ci[i, s])
+            else:
+                best = max(best, depth[i] + 1)
+    assert t.height == best
+
+
+# ---------------------------------------------------------------- spatial
+
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+@pytest.mark.parametrize("sort_queries", [True, False])
+def test_spatial_within_C1(orc, fmt, sort_queries):
+    pts, q = datagen.config_inputs("C1")
+    r = datagen.CONFIGS["C1"]["radius"]
+    t = abx.bvh_build(dev(pts), node_format=fmt)
+    off, idx = abx.query_spatial(t, dev(q), radius=r, sort_queries=sort_queries)
+    ex = check_spatial(orc, pts, 0, q, orc.WITHIN, host(off), host(idx), radius=r)
+    assert ex <= 20
+
+
+def test_spatial_within_boxes_and_radii(orc):
+    pts = datagen.uniform_cube(9000, 21)
+    boxes = datagen.boxes_around(pts, 22, 0.01)
+    q = datagen.uniform_cube(7001, 23)
+    radii = np.random.default_rng(24).uniform(-0.01, 0.05, size=7001).astype(np.float32)
+    for fmt in ("fp32", "q16"):
+        t = abx.bvh_build(dev(boxes), kind=1, node_format=fmt)
+        off, idx = abx.query_spatial(t, dev(q), radii=dev(radii))
+        check_spatial(orc, boxes, 1, q, orc.WITHIN, host(off), host(idx), radii=radii)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+def test_spatial_intersects_exact(orc, kind, fmt):
+    pts = datagen.clusters(11_000, 31)
+    prims = pts if kind == 0 else datagen.boxes_around(pts, 32, 0.005)
+    c = datagen.uniform_cube(6000, 33)
+    h = np.float32(datagen.box_side_for_density(11_000) / 2)
+    qb = np.concatenate([c - h, c + h], axis=1).astype(np.float32)
+    t = abx.bvh_build(dev(prims), kind=kind, node_format=fmt)
+    off, idx = abx.query_spatial(t, dev(qb), predicate="intersects")
+    assert check_spatial(orc, prims, kind, qb, orc.INTERSECTS, host(off), host(idx)) == 0
+
+
+def test_spatial_capacity_path(orc):
+    pts, q = datagen.config_inputs("C1", n=5000, m=3000)
+    t = abx.bvh_build(dev(pts))
+    off, idx = abx.query_spatial(t, dev(q), radius=0.1, capacity=10)     # too small
+    off2, idx2 = abx.query_spatial(t, dev(q), radius=0.1, capacity=10 ** 6)  # one pass
+    o, i = host(off), host(idx)
+    assert np.array_equal(o, host(off2))
+    for j in range(3000):
+        assert sorted(i[o[j]:o[j + 1]]) == sorted(host(idx2)[o[j]:o[j + 1]])
+    check_spatial(orc, pts, 0, q, orc.WITHIN, o, i, radius=0.1)
+
+
+def test_spatial_edge_cases(orc):
+    q = dev(datagen.uniform_cube(100, 1))
+    empty = abx.bvh_build(dev(np.zeros((0, 3), np.float32)))
+    off, idx = abx.query_spatial(empty, q, radius=1.0)
+    assert host(off).tolist() == [0] * 101 and idx.numel() == 0
+    one = abx.bvh_build(dev(np.array([[0.5, 0.5, 0.5]], np.float32)))
+    off, idx = abx.query_spatial(one, q, radius=0.3)
+    check_spatial(orc, np.array([[0.5, 0.5, 0.5]], np.float32), 0, host(q), orc.WITHIN, host(off),
+                  host(idx), radius=0.3)
+    t = abx.bvh_build(dev(datagen.uniform_cube(1000, 2)))
+    off, idx = abx.query_spatial(t, dev(np.zeros((0, 3), np.float32)), radius=1.0)
+    assert host(off).tolist() == [0]
+    off, idx = abx.query_spatial(t, q, radius=-1.0)
+    assert host(off).tolist() == [0] * 101
+
+
+# ---------------------------------------------------------------- nearest
+
+@pytest.mark.parametrize("k", [1, 5, 10, 16, 32])
+def test_nearest_C1(orc, k):
+    pts, q = datagen.config_inputs("C1")
+    t = abx.bvh_build(dev(pts))
+    off, idx, dist = abx.query_nearest(t, dev(q), k)
+    assert host(off).tolist() == list(range(0, k * len(q) + 1, k))
+    check_nearest(orc, pts, 0, q, k, host(idx), host(dist))
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_nearest_q16_and_boxes(orc, kind):
+    pts = datagen.clusters(10_007, 41)
+    prims = pts if kind == 0 else datagen.boxes_around(pts, 42, 0.004)
+    q = datagen.uniform_cube(5003, 43)
+    for fmt in ("fp32", "q16"):
+        t = abx.bvh_build(dev(prims), kind=kind, node_format=fmt)
+        off, idx, dist = abx.query_nearest(t, dev(q), 10)
+        check_nearest(orc, prims, kind, q, 10, host(idx), host(dist))
+
+
+def test_nearest_edge_cases(orc):
+    pts = datagen.uniform_cube(7, 1)
+    q = datagen.uniform_cube(50, 2)
+    t = abx.bvh_build(dev(pts))
+    off, idx, dist = abx.query_nearest(t, dev(q), 12)       # k > n: all n, purged rows
+    assert idx.shape == (50, 7)
+    check_nearest(orc, pts, 0, q, 12, host(idx), host(dist))
+    off, idx, dist = abx.query_nearest(t, dev(q), 0)
+    assert idx.shape == (50, 0) and host(off).tolist() == [0] * 51
+    empty = abx.bvh_build(dev(np.zeros((0, 3), np.float32)))
+    off, idx, dist = abx.query_nearest(empty, dev(q), 3)
+    assert idx.shape == (50, 0)
+    one = abx.bvh_build(dev(pts[:1]))
+    off, idx, dist = abx.query_nearest(one, dev(q), 3)
+    check_nearest(orc, pts[:1], 0, q, 3, host(idx), host(dist))
+    # duplicates: ties resolved by index
+    dup = np.repeat(pts, 5, axis=0)
+    t = abx.bvh_build(dev(dup))
+    off, idx, dist = abx.query_nearest(t, dev(q), 8)
+    oi, od = orc.nearest(dup, 0, q, 8)
+    assert np.array_equal(host(idx), oi)
+
+
+# ---------------------------------------------------------------- variants agree bitwise
+
+def test_variants_bitwise_equal(orc):
+    pts = datagen.shell(30_000, 51, 1 - 5e-3, 1 + 5e-3)
+    q = datagen.uniform_cube(20_000, 52, -1.0, 1.0)
+    r = float(np.float32(0.02))
+    res, csr = {}, None
+    for fmt in ("fp32", "q16"):
+        t = abx.bvh_build(dev(pts), node_format=fmt)
+        for sq in (True, False):
+            off, idx = abx.query_spatial(t, dev(q), radius=r, sort_queries=sq)
+            o, i = host(off), host(idx)
+            csr = csr or (o, i)
+            rows = [tuple(sorted(i[o[j]:o[j + 1]].tolist())) for j in range(len(q))]
+            _, ki, kd = abx.query_nearest(t, dev(q), 10, sort_queries=sq)
+            res[(fmt, sq)] = (o.tolist(), rows, host(ki).tobytes(), host(kd).tobytes())
+    first = next(iter(res.values()))
+    for v in res.values():
+        assert v == first
+    check_spatial(orc, pts, 0, q, orc.WITHIN, csr[0], csr[1], radius=r,
+                  rows=np.arange(0, 20_000, 97))
+
+
+def test_stats_consistent_with_results(orc):
+    pts, q = datagen.config_inputs("C1")
+    t = abx.bvh_build(dev(pts))
+    r = datagen.CONFIGS["C1"]["radius"]
+    st = host(abx.query_spatial_stats(t, dev(q), radius=r))
+    off, _ = abx.query_spatial(t, dev(q), radius=r)
+    # FP32 nodes: every emitted leaf is one leaf read
+    assert np.array_equal(st[:, 1], np.diff(host(off)))
+    assert np.all(st[:, 0] >= 1)
+    sn = host(abx.query_nearest_stats(t, dev(q), 10))
+    assert np.all(sn[:, 0] >= 1) and np.all(sn[:, 1] >= 10)

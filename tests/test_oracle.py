@@ -228,6 +228,13 @@ def test_refit_is_union_over_ranges(orc):
     np.testing.assert_array_equal(t["scene"][:3], pts.min(axis=0))
 
 
+def test_scene_box_flags_inverted_box(orc):
+    b = np.array([[0, 0, 0, 1, 1, 1], [0, 0, 0, 1, 1, 1]], np.float32)
+    assert not orc.scene_box(b, orc.BOXES)[1]
+    b[1, 4] = -0.5                      # hi.y < lo.y
+    assert orc.scene_box(b, orc.BOXES)[1]
+
+
 def test_scene_box_flags_nan_and_inf(orc):
     p = datagen.uniform_cube(10, 1)
     assert not orc.scene_box(p)[1]
