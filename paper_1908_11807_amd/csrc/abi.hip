@@ -16,10 +16,14 @@ int scene_blocks(int64_t n);
 abx_status launch_morton(int kind, const float *prims, int64_t n, const float *scene, int bits,
                          void *codes, bool wide, hipStream_t s);
 abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
-                         int32_t *parent_leaf, int32_t *parent_int, uint32_t *flags, hipStream_t s);
+                         int32_t *parent_leaf, int32_t *parent_int, int32_t *other_end,
+                         uint32_t *flags, hipStream_t s);
 abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
-                        const int32_t *parent_leaf, const int32_t *parent_int, NodeF32 *nodes,
-                        uint32_t *flags, TreeHeader *hdr, void *q16_leaves, hipStream_t s);
+                        const int32_t *parent_leaf, const int32_t *parent_int,
+                        const int32_t *other_end, NodeF32 *nodes, uint32_t *flags,
+                        TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
+                        uint32_t *frontier_count, hipStream_t s);
+size_t refit_frontier_cap(int64_t n);
 abx_status launch_quantise(const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
                            hipStream_t s);
 // traverse.hip
@@ -65,7 +69,8 @@ struct BuildLayout {
   size_t node_bytes, leaf_bytes;
   size_t nodes_off, leaves_off, tree_total;
   // scratch
-  size_t partial, codes, sorted, perm, parent_leaf, parent_int, flags, staging, sort, scratch_total;
+  size_t partial, codes, sorted, perm, parent_leaf, parent_int, other_end, flags, frontier,
+      staging, sort, scratch_total;
 };
 
 int resolve_bits(const abx_build_options *o) { return (o == nullptr || o->morton_bits == 0) ? 21 : o->morton_bits; }
@@ -114,8 +119,12 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   off = align_up(off + n * 4, 256);
   L.parent_int = off;
   off = align_up(off + n * 4, 256);
+  L.other_end = off;
+  off = align_up(off + n * 4, 256);
   L.flags = off;
   off = align_up(off + n * 4, 256);
+  L.frontier = off;
+  off = align_up(off + 256 + refit_frontier_cap(L.n) * 4, 256);
   L.staging = off;
   off = align_up(off + (L.q16 ? (size_t)L.ni * sizeof(NodeF32) : 0), 256);
   L.sort = off;
@@ -276,14 +285,18 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
                           : reinterpret_cast<NodeF32 *>(tree + L.nodes_off);
   int32_t *parent_leaf = reinterpret_cast<int32_t *>(sc + L.parent_leaf);
   int32_t *parent_int = reinterpret_cast<int32_t *>(sc + L.parent_int);
+  int32_t *other_end = reinterpret_cast<int32_t *>(sc + L.other_end);
   uint32_t *flags = reinterpret_cast<uint32_t *>(sc + L.flags);
   if (n > 0) {
     ABX_TRY(launch_morton(kind, prims->data, n, hdr->scene, L.bits, sc + L.codes, L.wide, s));
     ABX_TRY(radix_sort(sc + L.codes, nullptr, n, 3 * L.bits, sc + L.sorted, perm, sc + L.sort,
                        radix_sort_scratch_bytes(n, 3 * L.bits), s));
-    ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, fnodes, parent_leaf, parent_int, flags, s));
-    ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, parent_leaf, parent_int, fnodes, flags,
-                         hdr, tree + L.leaves_off, s));
+    ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, fnodes, parent_leaf, parent_int, other_end,
+                          flags, s));
+    uint32_t *fcount = reinterpret_cast<uint32_t *>(sc + L.frontier);
+    int32_t *frontier = reinterpret_cast<int32_t *>(sc + L.frontier + 256);
+    ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, parent_leaf, parent_int, other_end,
+                         fnodes, flags, hdr, tree + L.leaves_off, frontier, fcount, s));
     if (L.q16)
       ABX_TRY(launch_quantise(fnodes, L.ni, hdr, reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
   }

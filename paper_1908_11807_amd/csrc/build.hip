@@ -175,13 +175,15 @@ __device__ __forceinline__ int delta(const K *__restrict__ keys, int64_t n, int6
 // One thread per internal node i: direction from the neighbours, range end
 // by exponential then binary search, split by binary search on the prefix,
 // children at gamma / gamma+1 (leaf when the child range has one element).
-// Writes the two child references, the parents (parent<<1 | side) and clears
-// the node's arrival counter.
+// Writes the two child references, the parents (parent<<1 | side), the far
+// end j of the node's range [min(i,j), max(i,j)] and clears the node's
+// arrival counter.
 template <typename K>
 __global__ __launch_bounds__(kBuildBlock) void k_karras(const K *__restrict__ keys, int64_t n,
                                                         NodeF32 *__restrict__ nodes,
                                                         int32_t *__restrict__ parent_leaf,
                                                         int32_t *__restrict__ parent_int,
+                                                        int32_t *__restrict__ other_end,
                                                         uint32_t *__restrict__ flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1) return;
@@ -209,6 +211,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_karras(const K *__restrict__ ke
   const int32_t pl = (int32_t)(i << 1), pr = (int32_t)((i << 1) | 1);
   if (left_leaf) parent_leaf[gamma] = pl; else parent_int[gamma] = pl;
   if (right_leaf) parent_leaf[gamma + 1] = pr; else parent_int[gamma + 1] = pr;
+  other_end[i] = (int32_t)j;
   flags[i] = 0;
 }
 
@@ -229,68 +232,140 @@ __device__ __forceinline__ void load_child(const NodeF32 *node, int side, float 
   h = reinterpret_cast<const int *>(node)[14 + side];
 }
 
-// One thread per leaf (sorted position p).  The thread writes its box into
-// its slot of the parent node, then bumps the parent's arrival counter: the
-// first arrival stops, the second unions both children and climbs.  The
-// counter update is an acquire-release atomic at agent scope, which orders
-// the box stores before it and the sibling-box loads after it across the
-// XCDs' L2 caches.  For Q16 trees the leaf record (exact box + index) is
-// written here too.
+// Bottom-up refit in two launches.  One thread per leaf climbs from its
+// leaf: at each parent it writes its box into its child slot, then counts
+// its arrival; the first arrival stops, the second unions both children and
+// climbs on.  For Q16 trees the leaf record is written here too.
+//
+// Phase 1: each workgroup owns a chunk of kRefitChunk consecutive leaves (in
+// sorted order).  An internal node whose leaf range lies inside the chunk has
+// both children climbed by threads of the same workgroup, so the hand-off is
+// synchronised at workgroup scope (arrival counter in LDS; the sibling's box
+// is read back from the node in global memory, ordered by the counter's
+// acquire-release).  A thread that reaches a node whose range crosses the
+// chunk boundary stops there and appends (node, side) to the frontier list.
+// Phase 2 (one workgroup, after the kernel boundary has made phase 1's
+// stores visible): climbs from every frontier entry through the crossing
+// nodes, again with workgroup-scope synchronisation.  No step needs
+// agent-scope fences (which would write back and invalidate the XCDs' L2s).
+constexpr int kRefitThreads = 1024;
+constexpr int kRefitPerThread = 8;
+constexpr int kRefitChunk = kRefitThreads * kRefitPerThread;
+constexpr int kRefitMaxSteps = 256;  // > any tree height; only bounds the loops
+
 template <int KIND, bool kQ16>
-__global__ __launch_bounds__(kBuildBlock) void k_refit(const float *__restrict__ prims,
-                                                       const int32_t *__restrict__ perm, int64_t n,
-                                                       const int32_t *__restrict__ parent_leaf,
-                                                       const int32_t *__restrict__ parent_int,
-                                                       NodeF32 *nodes, uint32_t *flags,
-                                                       TreeHeader *hdr, void *q16_leaves) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int32_t orig = perm[p];
-  float b[6];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    b[a] = KIND == ABX_PRIM_POINTS ? prims[3 * (int64_t)orig + a] : prims[6 * (int64_t)orig + a];
-    b[3 + a] = KIND == ABX_PRIM_POINTS ? b[a] : prims[6 * (int64_t)orig + 3 + a];
-  }
-  if (kQ16) {
-    if (KIND == ABX_PRIM_POINTS) {
-      reinterpret_cast<float4 *>(q16_leaves)[p] = make_float4(b[0], b[1], b[2], __int_as_float(orig));
-    } else {
-      float4 *o = reinterpret_cast<float4 *>(q16_leaves) + 2 * p;
-      o[0] = make_float4(b[0], b[1], b[2], b[3]);
-      o[1] = make_float4(b[4], b[5], __int_as_float(orig), 0.0f);
-    }
-  }
-  if (n == 1) return;
-  int h = 0;
-  int32_t pp = parent_leaf[p];
-  // a well-formed tree is climbed in at most `height` steps (< 128); the
-  // bound only guarantees termination, a violation is reported as bad = 4
-  for (int step = 0;; ++step) {
-    if (step >= 256) {
-      atomicOr(&hdr->bad, 4);
-      return;
-    }
-    const int32_t parent = pp >> 1, side = pp & 1;
-    store_child(nodes + parent, side, b, h);
-    const uint32_t old = __hip_atomic_fetch_add(flags + parent, 1u, __ATOMIC_ACQ_REL,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    if (old == 0) return;
-    float sb[6];
-    int sh;
-    load_child(nodes + parent, side ^ 1, sb, sh);
+__global__ __launch_bounds__(kRefitThreads) void k_refit_local(
+    const float *__restrict__ prims, const int32_t *__restrict__ perm, int64_t n,
+    const int32_t *__restrict__ parent_leaf, const int32_t *__restrict__ parent_int,
+    const int32_t *__restrict__ other_end, NodeF32 *nodes, TreeHeader *hdr, void *q16_leaves,
+    int32_t *__restrict__ frontier, uint32_t *__restrict__ frontier_count, uint32_t frontier_cap) {
+  __shared__ uint32_t s_cnt[kRefitChunk];
+  for (int i = threadIdx.x; i < kRefitChunk; i += kRefitThreads) s_cnt[i] = 0;
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kRefitChunk;
+  for (int r = 0; r < kRefitPerThread; ++r) {
+    const int64_t p = c0 + (int64_t)r * kRefitThreads + threadIdx.x;
+    if (p >= n) return;
+    const int32_t orig = perm[p];
+    float b[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      b[a] = fminf(b[a], sb[a]);
-      b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+      b[a] = KIND == ABX_PRIM_POINTS ? prims[3 * (int64_t)orig + a] : prims[6 * (int64_t)orig + a];
+      b[3 + a] = KIND == ABX_PRIM_POINTS ? b[a] : prims[6 * (int64_t)orig + 3 + a];
     }
-    h = (h > sh ? h : sh) + 1;
-    if (parent == 0) {
-      hdr->height = h;
-      return;
+    if (kQ16) {
+      if (KIND == ABX_PRIM_POINTS) {
+        reinterpret_cast<float4 *>(q16_leaves)[p] =
+            make_float4(b[0], b[1], b[2], __int_as_float(orig));
+      } else {
+        float4 *o = reinterpret_cast<float4 *>(q16_leaves) + 2 * p;
+        o[0] = make_float4(b[0], b[1], b[2], b[3]);
+        o[1] = make_float4(b[4], b[5], __int_as_float(orig), 0.0f);
+      }
     }
-    pp = parent_int[parent];
+    if (n == 1) return;
+    int h = 0;
+    int32_t pp = parent_leaf[p];
+    for (int step = 0; step < kRefitMaxSteps; ++step) {
+      const int32_t parent = pp >> 1, side = pp & 1;
+      store_child(nodes + parent, side, b, h);
+      const int64_t j = other_end[parent];
+      const int64_t f = parent < j ? parent : j, l = parent < j ? j : parent;
+      if (f < c0 || l >= c0 + kRefitChunk) {
+        const uint32_t e = atomicAdd(frontier_count, 1u);
+        if (e < frontier_cap) frontier[e] = pp;
+        else atomicOr(&hdr->bad, 4);
+        break;
+      }
+      const uint32_t old = __hip_atomic_fetch_add(&s_cnt[parent - c0], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      float sb[6];
+      int sh;
+      load_child(nodes + parent, side ^ 1, sb, sh);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], sb[a]);
+        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+      }
+      h = (h > sh ? h : sh) + 1;
+      if (parent == 0) {
+        hdr->height = h;
+        break;
+      }
+      pp = parent_int[parent];
+      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
   }
+}
+
+// Phase 2: one workgroup climbs the nodes that cross chunk boundaries.
+// The arrival counters are the global `flags` (cleared by the hierarchy
+// kernel); every hand-off is between threads of this one workgroup.
+__global__ __launch_bounds__(kRefitThreads) void k_refit_top(const int32_t *__restrict__ parent_int,
+                                                             NodeF32 *nodes, uint32_t *flags,
+                                                             TreeHeader *hdr,
+                                                             const int32_t *__restrict__ frontier,
+                                                             const uint32_t *__restrict__ frontier_count,
+                                                             uint32_t frontier_cap) {
+  const uint32_t cnt = min(*frontier_count, frontier_cap);
+  for (uint32_t e = threadIdx.x; e < cnt; e += kRefitThreads) {
+    int32_t pp = frontier[e];
+    int32_t parent = pp >> 1, side = pp & 1;
+    float b[6];
+    int h;
+    load_child(nodes + parent, side, b, h);
+    for (int step = 0; step < kRefitMaxSteps; ++step) {
+      const uint32_t old = __hip_atomic_fetch_add(flags + parent, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      float sb[6];
+      int sh;
+      load_child(nodes + parent, side ^ 1, sb, sh);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], sb[a]);
+        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+      }
+      h = (h > sh ? h : sh) + 1;
+      if (parent == 0) {
+        hdr->height = h;
+        break;
+      }
+      pp = parent_int[parent];
+      parent = pp >> 1;
+      side = pp & 1;
+      store_child(nodes + parent, side, b, h);
+      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+}
+
+// frontier entries: a crossing node has at most two, and every crossing node
+// lies on the root path of some chunk boundary
+size_t refit_frontier_cap(int64_t n) {
+  const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
+  return (size_t)(2 * 128 * chunks + 64);
 }
 
 // ------------------------------------------------------------ Q16 nodes
@@ -379,38 +454,49 @@ abx_status launch_morton(int kind, const float *prims, int64_t n, const float *s
 }
 
 abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
-                         int32_t *parent_leaf, int32_t *parent_int, uint32_t *flags,
-                         hipStream_t s) {
+                         int32_t *parent_leaf, int32_t *parent_int, int32_t *other_end,
+                         uint32_t *flags, hipStream_t s) {
   if (n < 2) return ABX_OK;
   const unsigned g = grid_for(n - 1, kBuildBlock);
   if (wide)
     return launch("karras", s, [&] {
       k_karras<uint64_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint64_t *>(keys), n, nodes,
-                                                   parent_leaf, parent_int, flags);
+                                                   parent_leaf, parent_int, other_end, flags);
     });
   return launch("karras", s, [&] {
     k_karras<uint32_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint32_t *>(keys), n, nodes,
-                                                 parent_leaf, parent_int, flags);
+                                                 parent_leaf, parent_int, other_end, flags);
   });
 }
 
 abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
-                        const int32_t *parent_leaf, const int32_t *parent_int, NodeF32 *nodes,
-                        uint32_t *flags, TreeHeader *hdr, void *q16_leaves, hipStream_t s) {
+                        const int32_t *parent_leaf, const int32_t *parent_int,
+                        const int32_t *other_end, NodeF32 *nodes, uint32_t *flags,
+                        TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
+                        uint32_t *frontier_count, hipStream_t s) {
   if (n == 0) return ABX_OK;
-  const unsigned g = grid_for(n, kBuildBlock);
-#define ABX_REFIT(KD, QQ)                                                                       \
-  return launch("refit", s, [&] {                                                              \
-    k_refit<KD, QQ><<<g, kBuildBlock, 0, s>>>(prims, perm, n, parent_leaf, parent_int, nodes,  \
-                                              flags, hdr, q16_leaves);                          \
-  })
+  const unsigned g = grid_for(n, kRefitChunk);
+  const uint32_t cap = (uint32_t)refit_frontier_cap(n);
+  ABX_TRY(fill_u32(frontier_count, 0, 1, s));
+#define ABX_REFIT(KD, QQ)                                                                        \
+  ABX_TRY(launch("refit", s, [&] {                                                              \
+    k_refit_local<KD, QQ><<<g, kRefitThreads, 0, s>>>(prims, perm, n, parent_leaf, parent_int, \
+                                                       other_end, nodes, hdr, q16_leaves,       \
+                                                       frontier, frontier_count, cap);          \
+  }))
   if (kind == ABX_PRIM_POINTS) {
     if (q16) ABX_REFIT(ABX_PRIM_POINTS, true);
-    ABX_REFIT(ABX_PRIM_POINTS, false);
+    else ABX_REFIT(ABX_PRIM_POINTS, false);
+  } else {
+    if (q16) ABX_REFIT(ABX_PRIM_BOXES, true);
+    else ABX_REFIT(ABX_PRIM_BOXES, false);
   }
-  if (q16) ABX_REFIT(ABX_PRIM_BOXES, true);
-  ABX_REFIT(ABX_PRIM_BOXES, false);
 #undef ABX_REFIT
+  if (n <= kRefitChunk) return ABX_OK;
+  return launch("refit_top", s, [&] {
+    k_refit_top<<<1, kRefitThreads, 0, s>>>(parent_int, nodes, flags, hdr, frontier,
+                                            frontier_count, cap);
+  });
 }
 
 abx_status launch_quantise(const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
