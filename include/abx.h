@@ -176,6 +176,16 @@ abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, 
                              int32_t *offsets /*[m+1]*/, int32_t *indices, float *distances,
                              abx_stream_t stream);
 
+/* -- load balance of nearest queries ------------------------------------------
+ * A nearest query is first walked by one lane (the paper's batched mode).  A
+ * walk that exceeds `visits` internal-node visits is abandoned and the query
+ * is answered again by a whole wavefront (64 lanes sharing one query: the
+ * frontier is split among the lanes, their pruning bound is shared, their
+ * candidate lists are merged exactly).  Results do not depend on the value.
+ * abx_set_nearest_budget sets the process-wide budget (<= 0: unlimited, i.e.
+ * one lane per query throughout) and returns the previous one.  Default 4096. */
+int64_t abx_set_nearest_budget(int64_t visits);
+
 /* -- traversal statistics ---------------------------------------------------
  * Same traversals run in a counting mode: stats[2*i] = internal nodes
  * visited by query i (caller's order), stats[2*i+1] = leaf records read.

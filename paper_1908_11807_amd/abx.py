@@ -105,6 +105,8 @@ def _lib():
         L.abx_status_string.restype = C.c_char_p
         L.abx_version.restype = C.c_char_p
         L.abx_last_hip_error.restype = C.c_int
+        L.abx_set_nearest_budget.argtypes = [C.c_int64]
+        L.abx_set_nearest_budget.restype = C.c_int64
         L.abx_timing_enable.argtypes = [C.c_int]
         L.abx_timing_enable.restype = None
         L.abx_timing_reset.restype = None
@@ -328,6 +330,13 @@ def radix_sort_pairs(keys, key_bits, vals=None):
     _check(L.abx_radix_sort_pairs(_ptr(keys), _ptr(vin), n, int(key_bits), _ptr(kout), _ptr(vout),
                                   _ptr(scratch), sb.value, _stream()), "abx_radix_sort_pairs")
     return kout, vout
+
+
+def set_nearest_budget(visits):
+    """Node visits before a nearest query moves to the cooperative (one
+    wavefront per query) pass; <= 0 keeps every query on one lane.  Returns
+    the previous value."""
+    return int(_lib().abx_set_nearest_budget(int(visits)))
 
 
 def timing_enable(on=True):

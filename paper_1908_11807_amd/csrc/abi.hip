@@ -1,5 +1,6 @@
 // C-ABI of libabx: argument validation, buffer layout, the launch sequence of
 // each entry point and the diagnostics.  No device memory is allocated here.
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <string>
@@ -33,7 +34,8 @@ abx_status launch_spatial(const abx_bvh *b, int pred, const float *data, int64_t
                           const float *radii, float radius, const int32_t *order, int mode,
                           int32_t *counts, const int32_t *offsets, int32_t *indices, hipStream_t s);
 abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order,
-                          int k, int32_t *idx, float *dist, int32_t *stats, hipStream_t s);
+                          int k, int32_t *idx, float *dist, int32_t *stats, int32_t *heavy_q,
+                          float *heavy_bound, uint32_t *counters, int64_t budget, hipStream_t s);
 int max_tree_depth();
 
 namespace {
@@ -49,6 +51,11 @@ std::vector<Pending> g_pending;
 std::map<std::string, std::pair<double, int64_t>> g_acc;
 
 constexpr int64_t kMaxCount = INT32_MAX;
+
+// node visits after which a nearest query leaves the one-lane pass for the
+// cooperative pass (abx_set_nearest_budget)
+std::atomic<int64_t> g_nearest_budget{4096};
+int64_t nearest_budget() { return g_nearest_budget.load(std::memory_order_relaxed); }
 
 __global__ void k_row_offsets(int32_t *off, int64_t m, int32_t k) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -135,7 +142,7 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
 
 // ---------------------------------------------------------------- queries
 struct QueryLayout {
-  size_t codes, sorted, order, counts, total, scan, sort, bytes;
+  size_t codes, sorted, order, counts, total, scan, sort, heavy_q, heavy_bound, bytes;
 };
 
 QueryLayout query_layout(int64_t m) {
@@ -156,6 +163,10 @@ QueryLayout query_layout(int64_t m) {
   off = align_up(off + scan_scratch_bytes(m), 256);
   L.sort = off;
   off = align_up(off + radix_sort_scratch_bytes(m, 30), 256);
+  L.heavy_q = off;
+  off = align_up(off + mm * 4, 256);
+  L.heavy_bound = off;
+  off = align_up(off + mm * 4, 256);
   L.bytes = off;
   return L;
 }
@@ -218,6 +229,10 @@ const char *abx_status_string(abx_status s) {
 }
 
 int abx_last_hip_error(void) { return g_last_hip; }
+
+int64_t abx_set_nearest_budget(int64_t visits) {
+  return g_nearest_budget.exchange(visits > 0 ? visits : INT64_MAX);
+}
 
 void abx_timing_enable(int on) { g_timing = on != 0; }
 
@@ -306,7 +321,9 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
   if (h.bad & 1) return ABX_ERR_INVALID_INPUT;
   if (h.bad & 4) return ABX_ERR_UNSUPPORTED;  // refit bound exceeded (malformed hierarchy)
   if ((h.bad & 2) && L.q16) return ABX_ERR_UNSUPPORTED;
-  if (h.height >= max_tree_depth() - 1) return ABX_ERR_UNSUPPORTED;
+  // traversal stacks hold at most height + 8 entries (8 = the cooperative
+  // pass's share of the initial frontier)
+  if (h.height + 8 >= max_tree_depth()) return ABX_ERR_UNSUPPORTED;
 
   abx_bvh *b = new (std::nothrow) abx_bvh;
   if (!b) return ABX_ERR_INVALID_ARG;
@@ -471,7 +488,10 @@ static abx_status nearest_common(const abx_bvh *bvh, const float *points, int64_
   if (kk == 0) return stats ? fill_u32(stats, 0, 2 * (size_t)m, s) : ABX_OK;
   const int32_t *order = nullptr;
   if (sort_queries) ABX_TRY(order_queries(bvh, points, m, 3, sc, L, &order, s));
-  return launch_nearest(bvh, points, m, order, (int)kk, indices, distances, stats, s);
+  return launch_nearest(bvh, points, m, order, (int)kk, indices, distances, stats,
+                        reinterpret_cast<int32_t *>(sc + L.heavy_q),
+                        reinterpret_cast<float *>(sc + L.heavy_bound),
+                        reinterpret_cast<uint32_t *>(sc + L.total), nearest_budget(), s);
 }
 
 abx_status abx_query_nearest(const abx_bvh *bvh, const float *points, int64_t m, int32_t k,

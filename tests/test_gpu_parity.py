@@ -307,3 +307,44 @@ def test_stats_consistent_with_results(orc):
     assert np.all(st[:, 0] >= 1)
     sn = host(abx.query_nearest_stats(t, dev(q), 10))
     assert np.all(sn[:, 0] >= 1) and np.all(sn[:, 1] >= 10)
+
+
+# ---------------------------------------------------------------- cooperative nearest pass
+
+@pytest.mark.parametrize("budget", [1, 7, 64])
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+def test_nearest_cooperative_pass(orc, budget, fmt):
+    # a tiny visit budget sends (almost) every query through the wavefront-
+    # per-query pass; results must match the oracle and the one-lane pass
+    pts = datagen.shell(20_000, 61, 1 - 5e-3, 1 + 5e-3)
+    q = datagen.uniform_cube(3001, 62, -1.0, 1.0)
+    t = abx.bvh_build(dev(pts), node_format=fmt)
+    old = abx.set_nearest_budget(0)
+    try:
+        _, i1, d1 = abx.query_nearest(t, dev(q), 10)
+        abx.set_nearest_budget(budget)
+        for k in (1, 10, 16):
+            _, ik, dk = abx.query_nearest(t, dev(q), k)
+            check_nearest(orc, pts, 0, q, k, host(ik), host(dk))
+            if k == 10:
+                assert np.array_equal(host(ik), host(i1)) and np.array_equal(host(dk), host(d1))
+    finally:
+        abx.set_nearest_budget(old)
+
+
+def test_nearest_cooperative_boxes_and_ties(orc):
+    pts = np.repeat(datagen.uniform_cube(2000, 71), 3, axis=0)     # triplicated points
+    boxes = datagen.boxes_around(datagen.clusters(6000, 72), 73, 0.01)
+    q = datagen.uniform_cube(999, 74)
+    old = abx.set_nearest_budget(3)
+    try:
+        t = abx.bvh_build(dev(pts))
+        _, i, d = abx.query_nearest(t, dev(q), 8)
+        oi, od = orc.nearest(pts, 0, q, 8)
+        assert np.array_equal(host(i), oi)
+        for fmt in ("fp32", "q16"):
+            t = abx.bvh_build(dev(boxes), kind=1, node_format=fmt)
+            _, i, d = abx.query_nearest(t, dev(q), 10)
+            check_nearest(orc, boxes, 1, q, 10, host(i), host(d))
+    finally:
+        abx.set_nearest_budget(old)
