@@ -183,7 +183,7 @@ abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, 
  * frontier is split among the lanes, their pruning bound is shared, their
  * candidate lists are merged exactly).  Results do not depend on the value.
  * abx_set_nearest_budget sets the process-wide budget (<= 0: unlimited, i.e.
- * one lane per query throughout) and returns the previous one.  Default 4096. */
+ * one lane per query throughout) and returns the previous one.  Default 16384. */
 int64_t abx_set_nearest_budget(int64_t visits);
 
 /* -- traversal statistics ---------------------------------------------------
@@ -212,6 +212,88 @@ abx_status abx_radix_sort_sizes(int64_t n, int32_t key_bits, size_t *scratch_byt
 abx_status abx_radix_sort_pairs(const void *keys_in, const int32_t *vals_in, int64_t n,
                                 int32_t key_bits, void *keys_out, int32_t *vals_out,
                                 void *scratch, size_t scratch_bytes, abx_stream_t stream);
+
+/* -- batched forest --------------------------------------------------------------
+ * T independent point sets ("trees", 1 <= T <= 512) of uneven sizes, built
+ * and queried together: the batched mode of section 2.2 applied across trees
+ * as well as queries.  Points of all trees are concatenated; tree t owns rows
+ * [offsets[t], offsets[t+1]) (empty trees allowed).  One construction over
+ * composite keys (tree id above an 18-bit-per-axis Morton code against the
+ * tree's own scene box) gives every tree its own subtree of one LBVH arena;
+ * one persistent launch answers the nearest queries of all trees.  Neither
+ * call synchronises the host, so both can be captured in a HIP graph
+ * (abx_graph_*); abx_forest_check reads the device status afterwards.
+ * The offsets are passed twice: a host copy (sizes and launch shapes) and a
+ * device copy (read by kernels); both must hold the same values and stay
+ * valid for the duration of the call. */
+typedef struct {
+  int32_t trees;
+  const int64_t *offsets_host; /* host   [T+1], offsets[0] = 0, non-decreasing */
+  const int64_t *offsets_dev;  /* device [T+1], same values                    */
+  const float *data;           /* device [offsets[T], 3] points                 */
+  abx_node_format node_format;
+} abx_forest_primitives;
+
+typedef struct {
+  const int64_t *offsets_host; /* host   [T+1]: tree t's queries are rows [o[t], o[t+1]) */
+  const int64_t *offsets_dev;  /* device [T+1]                                          */
+  const float *data;           /* device [offsets[T], 3] query points                   */
+} abx_forest_queries;
+
+/* Launch shape of the persistent forest query: workgroups per CU, tiles of
+ * 64 queries taken per queue access, and the node-visit budget before a
+ * query moves to the cooperative pass. */
+typedef struct {
+  int32_t blocks_per_cu;
+  int32_t tiles_per_grab;
+  int64_t budget;
+} abx_forest_config;
+
+typedef struct abx_forest abx_forest;
+
+abx_status abx_forest_build_sizes(const abx_forest_primitives *prims, size_t *tree_bytes /*host*/,
+                                  size_t *scratch_bytes /*host*/);
+/* Enqueues the construction; no host synchronisation.  The scratch buffer
+ * may be reused once the stream has passed the call. */
+abx_status abx_forest_build(const abx_forest_primitives *prims, void *tree_mem, size_t tree_bytes,
+                            void *scratch, size_t scratch_bytes, abx_stream_t stream,
+                            abx_forest **out /*host*/);
+/* Waits for the stream and reports the construction status:
+ * ABX_ERR_INVALID_INPUT for a NaN/Inf coordinate, ABX_ERR_UNSUPPORTED for a
+ * tree deeper than the traversal stacks, else ABX_OK. */
+abx_status abx_forest_check(const abx_forest *f, abx_stream_t stream);
+abx_status abx_forest_destroy(abx_forest *f);
+/* Scratch bytes of a forest nearest query, and (host) the total number of
+ * result entries: sum over trees of (queries of t) * min(k, n_t). */
+abx_status abx_forest_query_nearest_sizes(const abx_forest *f, const abx_forest_queries *q, int32_t k,
+                                          size_t *scratch_bytes /*host*/, int64_t *total /*host*/);
+/* k nearest points of each query among its own tree's points, ordered by
+ * (distance, index); indices are tree-local (0 .. n_t-1).  Rows follow the
+ * caller's query order; row i has min(k, n_t) entries starting at
+ * offsets[i]; offsets[M] = total.  `cfg` may be NULL (the tuned shape of
+ * abx_forest_autotune if any, else a default).  1 <= k <= 32. */
+abx_status abx_forest_query_nearest(const abx_forest *f, const abx_forest_queries *q, int32_t k,
+                                    const abx_forest_config *cfg, void *scratch, size_t scratch_bytes,
+                                    int32_t *offsets /*[M+1]*/, int32_t *indices, float *distances,
+                                    abx_stream_t stream);
+/* Times the forest nearest query over a grid of launch shapes (the output
+ * buffers are overwritten), keeps the fastest in the handle, writes it to
+ * *best and, when json_path is not NULL, appends every timing to that file
+ * as one JSON object. */
+abx_status abx_forest_autotune(abx_forest *f, const abx_forest_queries *q, int32_t k, void *scratch,
+                               size_t scratch_bytes, int32_t *offsets, int32_t *indices,
+                               float *distances, abx_stream_t stream, const char *json_path,
+                               abx_forest_config *best /*host*/);
+
+/* -- HIP graphs ------------------------------------------------------------------
+ * Capture of everything enqueued on `stream` between begin and end (no host
+ * synchronisation may happen in between: use the forest entry points, not
+ * abx_bvh_build / abx_query_spatial, which read results back).  The
+ * instantiated graph is replayed with abx_graph_launch. */
+abx_status abx_graph_begin(abx_stream_t stream);
+abx_status abx_graph_end(abx_stream_t stream, void **graph_exec /*host*/);
+abx_status abx_graph_launch(void *graph_exec, abx_stream_t stream);
+abx_status abx_graph_destroy(void *graph_exec);
 
 /* -- diagnostics -------------------------------------------------------------
  * abx_timing_enable(1) brackets every kernel launch with HIP events on the

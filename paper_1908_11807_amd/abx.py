@@ -60,6 +60,19 @@ class Predicates(C.Structure):
                 ("radius", C.c_float), ("sort_queries", C.c_int32)]
 
 
+class ForestPrimitives(C.Structure):
+    _fields_ = [("trees", C.c_int32), ("offsets_host", C.c_void_p), ("offsets_dev", C.c_void_p),
+                ("data", C.c_void_p), ("node_format", C.c_int)]
+
+
+class ForestQueries(C.Structure):
+    _fields_ = [("offsets_host", C.c_void_p), ("offsets_dev", C.c_void_p), ("data", C.c_void_p)]
+
+
+class ForestConfig(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("tiles_per_grab", C.c_int32), ("budget", C.c_int64)]
+
+
 class Layout(C.Structure):
     _fields_ = [("n", C.c_int64), ("kind", C.c_int32), ("node_format", C.c_int32),
                 ("morton_bits", C.c_int32), ("height", C.c_int32), ("scene", C.c_float * 6),
@@ -96,6 +109,19 @@ def _lib():
             "abx_radix_sort_sizes": [i64, i32, P(sz)],
             "abx_radix_sort_pairs": [vp, vp, i64, i32, vp, vp, vp, sz, vp],
             "abx_timing_get": [C.c_char_p, P(C.c_double), P(i64)],
+            "abx_forest_build_sizes": [P(ForestPrimitives), P(sz), P(sz)],
+            "abx_forest_build": [P(ForestPrimitives), vp, sz, vp, sz, vp, P(vp)],
+            "abx_forest_check": [vp, vp],
+            "abx_forest_destroy": [vp],
+            "abx_forest_query_nearest_sizes": [vp, P(ForestQueries), i32, P(sz), P(i64)],
+            "abx_forest_query_nearest": [vp, P(ForestQueries), i32, P(ForestConfig), vp, sz, vp, vp,
+                                         vp, vp],
+            "abx_forest_autotune": [vp, P(ForestQueries), i32, vp, sz, vp, vp, vp, vp, C.c_char_p,
+                                    P(ForestConfig)],
+            "abx_graph_begin": [vp],
+            "abx_graph_end": [vp, P(vp)],
+            "abx_graph_launch": [vp, vp],
+            "abx_graph_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -330,6 +356,142 @@ def radix_sort_pairs(keys, key_bits, vals=None):
     _check(L.abx_radix_sort_pairs(_ptr(keys), _ptr(vin), n, int(key_bits), _ptr(kout), _ptr(vout),
                                   _ptr(scratch), sb.value, _stream()), "abx_radix_sort_pairs")
     return kout, vout
+
+
+class ForestPlan:
+    """A batched forest (section 2.2 batched mode across trees) with every
+    device buffer allocated up front, so that the build and the query can be
+    replayed eagerly or captured once in a HIP graph and replayed.
+
+    points: float32 CUDA [N, 3]; offsets: int sequence [T+1] (tree t owns
+    rows offsets[t]..offsets[t+1]); queries/query_offsets likewise; k <= 32.
+    Results (after run() or a replay): self.offsets int32 [M+1],
+    self.indices int32 [total] (tree-local), self.distances float32 [total].
+    """
+
+    def __init__(self, points, offsets, queries, query_offsets, k, node_format="q16"):
+        import numpy as np
+        L = _lib()
+        self.k = int(k)
+        self.points = _dev_f32(points, 3, "points")
+        self.queries = _dev_f32(queries, 3, "queries")
+        dev = self.points.device
+        self._off_h = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self._qoff_h = np.ascontiguousarray(np.asarray(query_offsets, dtype=np.int64))
+        self.trees = self._off_h.shape[0] - 1
+        if self._qoff_h.shape[0] != self.trees + 1:
+            raise ValueError("query_offsets must have one entry per tree plus one")
+        self._off_d = torch.from_numpy(self._off_h).to(dev)
+        self._qoff_d = torch.from_numpy(self._qoff_h).to(dev)
+        self._prims = ForestPrimitives(self.trees, self._off_h.ctypes.data, self._off_d.data_ptr(),
+                                       self.points.data_ptr() if self.points.numel() else None,
+                                       _FORMATS[node_format])
+        self._q = ForestQueries(self._qoff_h.ctypes.data, self._qoff_d.data_ptr(),
+                                self.queries.data_ptr() if self.queries.numel() else None)
+        tb, sb = C.c_size_t(), C.c_size_t()
+        _check(L.abx_forest_build_sizes(C.byref(self._prims), C.byref(tb), C.byref(sb)),
+               "abx_forest_build_sizes")
+        self.tree = _bytes(tb.value, dev)
+        self._bscratch = _bytes(sb.value, dev)
+        self._tb, self._sb = tb.value, sb.value
+        self._h = None
+        self.build()                      # the handle (host metadata) exists from here on
+        qs, tot = C.c_size_t(), C.c_int64()
+        _check(L.abx_forest_query_nearest_sizes(self._h, C.byref(self._q), self.k, C.byref(qs),
+                                                C.byref(tot)), "abx_forest_query_nearest_sizes")
+        self._qscratch = _bytes(qs.value, dev)
+        self._qs = qs.value
+        self.total = tot.value
+        M = int(self._qoff_h[-1])
+        self.offsets = torch.empty(M + 1, dtype=torch.int32, device=dev)
+        self.indices = torch.empty(max(self.total, 1), dtype=torch.int32, device=dev)
+        self.distances = torch.empty(max(self.total, 1), dtype=torch.float32, device=dev)
+        self.config = None
+        self._graph = None
+
+    def build(self):
+        L = _lib()
+        h = C.c_void_p()
+        _check(L.abx_forest_build(C.byref(self._prims), _ptr(self.tree), self._tb, _ptr(self._bscratch),
+                                  self._sb, _stream(), C.byref(h)), "abx_forest_build")
+        if self._h:
+            cfg = getattr(self, "config", None)
+            L.abx_forest_destroy(self._h)
+            self._h = h
+            if cfg is not None:
+                self.config = cfg
+        else:
+            self._h = h
+
+    def check(self):
+        _check(_lib().abx_forest_check(self._h, _stream()), "abx_forest_check")
+
+    def query(self, config=None):
+        cfg = None
+        if config is not None:
+            cfg = ForestConfig(int(config["blocks_per_cu"]), int(config["tiles_per_grab"]),
+                               int(config["budget"]))
+        elif self.config is not None:
+            c = self.config
+            cfg = ForestConfig(c["blocks_per_cu"], c["tiles_per_grab"], c["budget"])
+        _check(_lib().abx_forest_query_nearest(self._h, C.byref(self._q), self.k,
+                                               C.byref(cfg) if cfg is not None else None,
+                                               _ptr(self._qscratch), self._qs, _ptr(self.offsets),
+                                               _ptr(self.indices), _ptr(self.distances), _stream()),
+               "abx_forest_query_nearest")
+
+    def run(self):
+        self.build()
+        self.query()
+        return self.results()
+
+    def results(self):
+        t = self.total
+        return self.offsets, self.indices[:t], self.distances[:t]
+
+    def autotune(self, json_path=None):
+        best = ForestConfig()
+        _check(_lib().abx_forest_autotune(self._h, C.byref(self._q), self.k, _ptr(self._qscratch),
+                                          self._qs, _ptr(self.offsets), _ptr(self.indices),
+                                          _ptr(self.distances), _stream(),
+                                          json_path.encode() if json_path else None, C.byref(best)),
+               "abx_forest_autotune")
+        self.config = dict(blocks_per_cu=best.blocks_per_cu, tiles_per_grab=best.tiles_per_grab,
+                           budget=best.budget)
+        return self.config
+
+    def capture(self, build=True):
+        """Capture (build +) query on the current stream (must not be the
+        null stream) into a HIP graph; replay with replay()."""
+        L = _lib()
+        _check(L.abx_graph_begin(_stream()), "abx_graph_begin")
+        try:
+            if build:
+                h2 = C.c_void_p()
+                st = L.abx_forest_build(C.byref(self._prims), _ptr(self.tree), self._tb,
+                                        _ptr(self._bscratch), self._sb, _stream(), C.byref(h2))
+                if h2:
+                    L.abx_forest_destroy(h2)   # host metadata only; self._h describes the same tree
+                _check(st, "abx_forest_build")
+            self.query()
+        finally:
+            g = C.c_void_p()
+            st = L.abx_graph_end(_stream(), C.byref(g))
+        _check(st, "abx_graph_end")
+        if self._graph:
+            L.abx_graph_destroy(self._graph)
+        self._graph = g
+
+    def replay(self):
+        _check(_lib().abx_graph_launch(self._graph, _stream()), "abx_graph_launch")
+
+    def __del__(self):
+        if _LIB is None:
+            return
+        if getattr(self, "_graph", None):
+            _LIB.abx_graph_destroy(self._graph)
+        if getattr(self, "_h", None):
+            _LIB.abx_forest_destroy(self._h)
 
 
 def set_nearest_budget(visits):

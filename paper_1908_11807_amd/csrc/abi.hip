@@ -54,7 +54,7 @@ constexpr int64_t kMaxCount = INT32_MAX;
 
 // node visits after which a nearest query leaves the one-lane pass for the
 // cooperative pass (abx_set_nearest_budget)
-std::atomic<int64_t> g_nearest_budget{4096};
+std::atomic<int64_t> g_nearest_budget{16384};
 int64_t nearest_budget() { return g_nearest_budget.load(std::memory_order_relaxed); }
 
 __global__ void k_row_offsets(int32_t *off, int64_t m, int32_t k) {
@@ -201,7 +201,14 @@ abx_status hip_fail(hipError_t e) {
   return ABX_ERR_HIP;
 }
 
-bool timing_on() { return g_timing; }
+namespace {
+bool g_capturing = false;
+}
+bool graph_capturing() { return g_capturing; }
+void set_graph_capturing(bool on) { g_capturing = on; }
+
+// no events inside a graph capture: timing is for eager launches only
+bool timing_on() { return g_timing && !g_capturing; }
 
 void timing_record(const char *name, hipEvent_t a, hipEvent_t b) {
   g_pending.push_back(Pending{name, a, b});

@@ -131,3 +131,21 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(abx, "_LIB", None)
     with pytest.raises(RuntimeError, match="not built"):
         abx.library()
+
+
+def test_forest_sizes_validation():
+    import numpy as np
+    abx, L = _lib()
+    off = np.array([0, 10, 10, 25], np.int64)
+    pr = abx.ForestPrimitives(3, off.ctypes.data, 1, 1, 0)
+    tb, sb = C.c_size_t(), C.c_size_t()
+    assert L.abx_forest_build_sizes(C.byref(pr), C.byref(tb), C.byref(sb)) == abx.OK
+    assert tb.value > 256 and sb.value > 0
+    bad = np.array([0, 10, 5, 25], np.int64)              # decreasing offsets
+    pr = abx.ForestPrimitives(3, bad.ctypes.data, 1, 1, 0)
+    assert L.abx_forest_build_sizes(C.byref(pr), C.byref(tb), C.byref(sb)) == abx.ERR_INVALID_ARG
+    pr = abx.ForestPrimitives(0, off.ctypes.data, 1, 1, 0)   # no trees
+    assert L.abx_forest_build_sizes(C.byref(pr), C.byref(tb), C.byref(sb)) == abx.ERR_INVALID_ARG
+    pr = abx.ForestPrimitives(513, off.ctypes.data, 1, 1, 0)  # too many trees
+    assert L.abx_forest_build_sizes(C.byref(pr), C.byref(tb), C.byref(sb)) == abx.ERR_INVALID_ARG
+    assert L.abx_graph_begin(None) == abx.ERR_INVALID_ARG     # null stream cannot be captured
