@@ -51,7 +51,8 @@ typedef enum {
   ABX_ERR_CAPACITY = 3,      /* result buffer too small; see query_spatial */
   ABX_ERR_OVERFLOW = 4,      /* a size or result count reaches 2^31        */
   ABX_ERR_HIP = 5,           /* a HIP runtime call failed                  */
-  ABX_ERR_UNSUPPORTED = 6    /* valid request this build does not handle   */
+  ABX_ERR_UNSUPPORTED = 6,   /* valid request this build does not handle   */
+  ABX_PENDING = 7            /* (server) the request has not completed yet */
 } abx_status;
 
 /* Primitives (section 2.1 "Construct AABBs": a point is a degenerate box). */
@@ -294,6 +295,78 @@ abx_status abx_graph_begin(abx_stream_t stream);
 abx_status abx_graph_end(abx_stream_t stream, void **graph_exec /*host*/);
 abx_status abx_graph_launch(void *graph_exec, abx_stream_t stream);
 abx_status abx_graph_destroy(void *graph_exec);
+
+/* -- serving -------------------------------------------------------------------
+ * Continuous batching of query requests against device-resident trees (a
+ * tree is built once and queried many times, section 2.2).  A scheduler
+ * thread owns `slots` HIP streams.  Requests wait in FIFO order; the head is
+ * admitted as soon as a slot is free and its device reservation fits in the
+ * caller's arena (the HBM budget), so requests that arrive while others run
+ * start as slots and memory free up, and their kernels overlap on the
+ * device.  Nearest requests run in one phase; radius requests in two (count,
+ * then fill once the exact result space is reserved).  Results are copied to
+ * a pinned host arena the server allocates at creation and stay valid until
+ * abx_server_release.  Every request is answered by the same kernels as the
+ * plain entry points, so its result does not depend on what else is in
+ * flight.  Times are seconds on abx_server_now()'s steady clock.
+ * Reservations (bytes, 256-B granules): queries 12m + query scratch +
+ * nearest 8mk' | radius offsets 4(m+1), then 4*total for the fill.
+ * `simulate` = 1 runs the scheduler without HIP (each phase lasts
+ * sim_ns_per_query * m ns, radius requests find 10 results per query): for
+ * testing admission and accounting on a machine without a GPU. */
+typedef enum { ABX_REQ_RADIUS = 0, ABX_REQ_NEAREST = 1 } abx_request_kind;
+
+typedef struct {
+  int32_t slots;          /* concurrent requests on the device, 1..64        */
+  void *arena;            /* device buffer for request data (caller-owned)   */
+  size_t arena_bytes;     /* its size: the HBM budget of in-flight requests  */
+  size_t host_bytes;      /* pinned host result arena allocated by the server */
+  int32_t poll_us;        /* scheduler sleep when idle-polling (0: 20 us)    */
+  int32_t simulate;
+  double sim_ns_per_query;
+} abx_server_config;
+
+typedef struct {
+  int32_t tree;            /* id from abx_server_add_tree                    */
+  abx_request_kind kind;
+  const float *queries;    /* HOST [m,3]; read while the request runs         */
+  int64_t m;
+  float radius;            /* radius requests                                */
+  int32_t k;               /* nearest requests, 0..32                        */
+  double t_arrival;        /* caller's arrival time (abx_server_now clock)   */
+} abx_request;
+
+typedef struct {
+  abx_status status;
+  int64_t m, total;                /* rows and result entries               */
+  const int32_t *offsets;          /* HOST [m+1] (pinned arena)             */
+  const int32_t *indices;          /* HOST [total]                          */
+  const float *distances;          /* HOST [total] (nearest) or NULL        */
+  double t_arrival, t_admit, t_done;
+} abx_result;
+
+typedef struct {
+  int64_t submitted, completed, failed, queries, max_in_flight, in_flight, queued;
+  size_t device_high_water, host_high_water;
+} abx_server_stats;
+
+typedef struct abx_server abx_server;
+
+abx_status abx_server_create(const abx_server_config *cfg, abx_server **out /*host*/);
+abx_status abx_server_add_tree(abx_server *srv, const abx_bvh *tree, int32_t *id /*host*/);
+/* Queues a copy of *req; returns at once.  ABX_ERR_CAPACITY is reported in
+ * the result of a request whose reservation can never fit. */
+abx_status abx_server_submit(abx_server *srv, const abx_request *req, uint64_t *ticket /*host*/);
+/* ABX_PENDING until the request has completed (results host-visible). */
+abx_status abx_server_poll(abx_server *srv, uint64_t ticket, abx_result *out /*host*/);
+abx_status abx_server_wait(abx_server *srv, uint64_t ticket, abx_result *out /*host*/);
+abx_status abx_server_release(abx_server *srv, uint64_t ticket);
+abx_status abx_server_drain(abx_server *srv);
+abx_status abx_server_get_stats(abx_server *srv, abx_server_stats *out /*host*/);
+/* Stops the scheduler: requests not yet on the device fail, running ones
+ * complete; then frees the streams and the pinned host arena. */
+abx_status abx_server_destroy(abx_server *srv);
+double abx_server_now(void);
 
 /* -- diagnostics -------------------------------------------------------------
  * abx_timing_enable(1) brackets every kernel launch with HIP events on the

@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libabx.so")
 
 # status codes (include/abx.h)
-OK, ERR_INVALID_ARG, ERR_INVALID_INPUT, ERR_CAPACITY, ERR_OVERFLOW, ERR_HIP, ERR_UNSUPPORTED = range(7)
+OK, ERR_INVALID_ARG, ERR_INVALID_INPUT, ERR_CAPACITY, ERR_OVERFLOW, ERR_HIP, ERR_UNSUPPORTED, PENDING = range(8)
 PRIM_POINTS, PRIM_BOXES = 0, 1
 NODES_FP32, NODES_Q16 = 0, 1
 PRED_WITHIN, PRED_INTERSECTS_BOX = 0, 1
@@ -71,6 +71,33 @@ class ForestQueries(C.Structure):
 
 class ForestConfig(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int32), ("tiles_per_grab", C.c_int32), ("budget", C.c_int64)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("arena", C.c_void_p), ("arena_bytes", C.c_size_t),
+                ("host_bytes", C.c_size_t), ("poll_us", C.c_int32), ("simulate", C.c_int32),
+                ("sim_ns_per_query", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("tree", C.c_int32), ("kind", C.c_int), ("queries", C.c_void_p), ("m", C.c_int64),
+                ("radius", C.c_float), ("k", C.c_int32), ("t_arrival", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("m", C.c_int64), ("total", C.c_int64),
+                ("offsets", C.c_void_p), ("indices", C.c_void_p), ("distances", C.c_void_p),
+                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queries", C.c_int64), ("max_in_flight", C.c_int64), ("in_flight", C.c_int64),
+                ("queued", C.c_int64), ("device_high_water", C.c_size_t),
+                ("host_high_water", C.c_size_t)]
+
+
+REQ_RADIUS, REQ_NEAREST = 0, 1
 
 
 class Layout(C.Structure):
@@ -118,6 +145,15 @@ def _lib():
                                          vp, vp],
             "abx_forest_autotune": [vp, P(ForestQueries), i32, vp, sz, vp, vp, vp, vp, C.c_char_p,
                                     P(ForestConfig)],
+            "abx_server_create": [P(ServerConfig), P(vp)],
+            "abx_server_add_tree": [vp, vp, P(i32)],
+            "abx_server_submit": [vp, P(Request), P(C.c_uint64)],
+            "abx_server_poll": [vp, C.c_uint64, P(Result)],
+            "abx_server_wait": [vp, C.c_uint64, P(Result)],
+            "abx_server_release": [vp, C.c_uint64],
+            "abx_server_drain": [vp],
+            "abx_server_get_stats": [vp, P(ServerStats)],
+            "abx_server_destroy": [vp],
             "abx_graph_begin": [vp],
             "abx_graph_end": [vp, P(vp)],
             "abx_graph_launch": [vp, vp],
@@ -131,6 +167,7 @@ def _lib():
         L.abx_status_string.restype = C.c_char_p
         L.abx_version.restype = C.c_char_p
         L.abx_last_hip_error.restype = C.c_int
+        L.abx_server_now.restype = C.c_double
         L.abx_set_nearest_budget.argtypes = [C.c_int64]
         L.abx_set_nearest_budget.restype = C.c_int64
         L.abx_timing_enable.argtypes = [C.c_int]
@@ -492,6 +529,108 @@ class ForestPlan:
             _LIB.abx_graph_destroy(self._graph)
         if getattr(self, "_h", None):
             _LIB.abx_forest_destroy(self._h)
+
+
+def server_now():
+    """Seconds on the server's steady clock (request arrival timestamps)."""
+    return float(_lib().abx_server_now())
+
+
+class Server:
+    """Continuous-batching request server over device-resident trees.
+
+    slots: concurrent requests (one HIP stream each); budget_bytes: the HBM
+    arena for in-flight request data (allocated here with PyTorch and handed
+    to the library); host_bytes: pinned host result arena (allocated by the
+    library).  simulate=True runs the scheduler without the GPU.
+    """
+
+    def __init__(self, slots=4, budget_bytes=1 << 30, host_bytes=1 << 30, simulate=False,
+                 sim_ns_per_query=0.0, poll_us=0, device="cuda"):
+        L = _lib()
+        self.arena = None if simulate else torch.empty(int(budget_bytes), dtype=torch.uint8, device=device)
+        cfg = ServerConfig(int(slots), self.arena.data_ptr() if self.arena is not None else None,
+                           int(budget_bytes), int(host_bytes), int(poll_us), 1 if simulate else 0,
+                           float(sim_ns_per_query))
+        h = C.c_void_p()
+        _check(L.abx_server_create(C.byref(cfg), C.byref(h)), "abx_server_create")
+        self._h = h
+        self._trees = []
+        self._inputs = {}
+
+    def add_tree(self, bvh):
+        tid = C.c_int32()
+        _check(_lib().abx_server_add_tree(self._h, bvh.handle if bvh is not None else None,
+                                          C.byref(tid)), "abx_server_add_tree")
+        self._trees.append(bvh)
+        return tid.value
+
+    def submit(self, tree, kind, queries, radius=0.0, k=0, t_arrival=None):
+        """queries: host float32 [m, 3] (numpy or CPU tensor; pinned is fastest).
+        Returns a ticket."""
+        if isinstance(queries, torch.Tensor):
+            if queries.is_cuda:
+                raise TypeError("server queries are host memory")
+            q = queries.contiguous()
+            ptr, m = (q.data_ptr() if q.numel() else None), q.numel() // 3
+        else:
+            import numpy as np
+            q = np.ascontiguousarray(queries, dtype=np.float32)
+            ptr, m = (q.ctypes.data if q.size else None), q.size // 3
+        req = Request(int(tree), int(kind), ptr, int(m), float(radius), int(k),
+                      float(server_now() if t_arrival is None else t_arrival))
+        t = C.c_uint64()
+        _check(_lib().abx_server_submit(self._h, C.byref(req), C.byref(t)), "abx_server_submit")
+        self._inputs[t.value] = q
+        return t.value
+
+    def _result(self, r, copy):
+        import numpy as np
+        out = dict(status=r.status, m=r.m, total=r.total, t_arrival=r.t_arrival,
+                   t_admit=r.t_admit, t_done=r.t_done)
+        if r.status == OK and copy:
+            def arr(ptr, n, ct, dt):
+                if not ptr or n == 0:
+                    return np.zeros(0, dt)
+                return np.ctypeslib.as_array(C.cast(ptr, C.POINTER(ct)), shape=(n,)).copy()
+            out["offsets"] = arr(r.offsets, r.m + 1, C.c_int32, np.int32)
+            out["indices"] = arr(r.indices, r.total, C.c_int32, np.int32)
+            out["distances"] = arr(r.distances, r.total, C.c_float, np.float32) if r.distances else None
+        return out
+
+    def poll(self, ticket, copy=True):
+        r = Result()
+        st = _lib().abx_server_poll(self._h, ticket, C.byref(r))
+        if st == PENDING:
+            return None
+        _check(st, "abx_server_poll")
+        return self._result(r, copy)
+
+    def wait(self, ticket, copy=True):
+        r = Result()
+        _check(_lib().abx_server_wait(self._h, ticket, C.byref(r)), "abx_server_wait")
+        return self._result(r, copy)
+
+    def release(self, ticket):
+        _check(_lib().abx_server_release(self._h, ticket), "abx_server_release")
+        self._inputs.pop(ticket, None)
+
+    def drain(self):
+        _check(_lib().abx_server_drain(self._h), "abx_server_drain")
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib().abx_server_get_stats(self._h, C.byref(st)), "abx_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().abx_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        if _LIB is not None:
+            self.close()
 
 
 def set_nearest_budget(visits):

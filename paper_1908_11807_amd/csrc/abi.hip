@@ -3,6 +3,7 @@
 #include <atomic>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -38,6 +39,11 @@ abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const i
                           float *heavy_bound, uint32_t *counters, int64_t budget, hipStream_t s);
 int max_tree_depth();
 
+// node visits after which a nearest query leaves the one-lane pass for the
+// cooperative pass (abx_set_nearest_budget)
+std::atomic<int64_t> g_nearest_budget{16384};
+int64_t nearest_budget() { return g_nearest_budget.load(std::memory_order_relaxed); }
+
 namespace {
 
 thread_local int g_last_hip = 0;
@@ -47,15 +53,11 @@ struct Pending {
   hipEvent_t a, b;
 };
 bool g_timing = false;
+std::mutex g_timing_mu;  // launches may come from the server's scheduler thread
 std::vector<Pending> g_pending;
 std::map<std::string, std::pair<double, int64_t>> g_acc;
 
 constexpr int64_t kMaxCount = INT32_MAX;
-
-// node visits after which a nearest query leaves the one-lane pass for the
-// cooperative pass (abx_set_nearest_budget)
-std::atomic<int64_t> g_nearest_budget{16384};
-int64_t nearest_budget() { return g_nearest_budget.load(std::memory_order_relaxed); }
 
 __global__ void k_row_offsets(int32_t *off, int64_t m, int32_t k) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -196,6 +198,57 @@ abx_status order_queries(const abx_bvh *b, const float *data, int64_t m, int wid
 
 }  // namespace
 
+// ---------------------------------------------------------------- internal enqueue sequences
+// Non-blocking pieces of the query entry points, shared with the server.
+size_t query_scratch_bytes(int64_t m) { return query_layout(m).bytes; }
+
+// Spatial count phase: optional Morton ordering, counting traversal, scan of
+// the counts into offsets[0..m]; *d_total receives the device address of the
+// int64 total (inside scratch).
+abx_status spatial_count_enqueue(const abx_bvh *bvh, const abx_predicates *p, char *sc,
+                                 int32_t *offsets, int64_t **d_total, hipStream_t s) {
+  const QueryLayout L = query_layout(p->m);
+  const int64_t m = p->m;
+  int64_t *tot = reinterpret_cast<int64_t *>(sc + L.total);
+  *d_total = tot;
+  if (bvh->n == 0 || m == 0) {
+    ABX_TRY(fill_u32(offsets, 0, (size_t)m + 1, s));
+    return fill_u32(tot, 0, 2, s);
+  }
+  const int width = p->kind == ABX_PRED_WITHIN ? 3 : 6;
+  const int32_t *order = nullptr;
+  if (p->sort_queries) ABX_TRY(order_queries(bvh, p->data, m, width, sc, L, &order, s));
+  int32_t *counts = reinterpret_cast<int32_t *>(sc + L.counts);
+  ABX_TRY(launch_spatial(bvh, p->kind, p->data, m, p->radii, p->radius, order, 0 /*count*/, counts,
+                         nullptr, nullptr, s));
+  return exclusive_scan(counts, m, offsets, tot, sc + L.scan, scan_scratch_bytes(m), s);
+}
+
+// Spatial fill phase, after spatial_count_enqueue on the same scratch.
+abx_status spatial_fill_enqueue(const abx_bvh *bvh, const abx_predicates *p, char *sc,
+                                const int32_t *offsets, int32_t *indices, hipStream_t s) {
+  if (bvh->n == 0 || p->m == 0) return ABX_OK;
+  const QueryLayout L = query_layout(p->m);
+  const int32_t *order = p->sort_queries ? reinterpret_cast<const int32_t *>(sc + L.order) : nullptr;
+  return launch_spatial(bvh, p->kind, p->data, p->m, p->radii, p->radius, order, 1 /*fill*/, nullptr,
+                        offsets, indices, s);
+}
+
+// Nearest queries: rows of min(k, n) entries; offsets optional.
+abx_status nearest_enqueue(const abx_bvh *bvh, const float *pts, int64_t m, int32_t k, int sort,
+                           char *sc, int32_t *offsets, int32_t *indices, float *dist, hipStream_t s) {
+  const QueryLayout L = query_layout(m);
+  const int64_t kk = k < bvh->n ? k : bvh->n;
+  if (offsets) ABX_TRY(row_offsets(offsets, m, (int32_t)kk, s));
+  if (m == 0 || kk == 0) return ABX_OK;
+  const int32_t *order = nullptr;
+  if (sort) ABX_TRY(order_queries(bvh, pts, m, 3, sc, L, &order, s));
+  return launch_nearest(bvh, pts, m, order, (int)kk, indices, dist, nullptr,
+                        reinterpret_cast<int32_t *>(sc + L.heavy_q),
+                        reinterpret_cast<float *>(sc + L.heavy_bound),
+                        reinterpret_cast<uint32_t *>(sc + L.total), nearest_budget(), s);
+}
+
 abx_status hip_fail(hipError_t e) {
   g_last_hip = (int)e;
   return ABX_ERR_HIP;
@@ -211,6 +264,7 @@ void set_graph_capturing(bool on) { g_capturing = on; }
 bool timing_on() { return g_timing && !g_capturing; }
 
 void timing_record(const char *name, hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
   g_pending.push_back(Pending{name, a, b});
 }
 
@@ -231,6 +285,7 @@ const char *abx_status_string(abx_status s) {
     case ABX_ERR_OVERFLOW: return "size or result count reaches 2^31";
     case ABX_ERR_HIP: return "HIP runtime error";
     case ABX_ERR_UNSUPPORTED: return "unsupported request";
+    case ABX_PENDING: return "pending";
   }
   return "unknown status";
 }
@@ -244,6 +299,7 @@ int64_t abx_set_nearest_budget(int64_t visits) {
 void abx_timing_enable(int on) { g_timing = on != 0; }
 
 static void timing_flush() {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
   for (auto &p : g_pending) {
     float ms = 0.0f;
     if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {

@@ -1,0 +1,96 @@
+"""GPU serving loop: every request's result is the same alone and in a mix
+of concurrent requests, and matches the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1908_11807_amd import abx, datagen
+from parity import check_nearest, check_spatial
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["radius", 1, 8, 32]
+
+
+def _setup():
+    cube = datagen.uniform_cube(20_000, 5)
+    shell = datagen.shell(20_000, 6, 1 - 5e-3, 1 + 5e-3)
+    trees = [abx.bvh_build(torch.from_numpy(cube).cuda(), node_format="fp32"),
+             abx.bvh_build(torch.from_numpy(shell).cuda(), node_format="q16")]
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(40):
+        t = int(rng.integers(0, 2))
+        m = int(np.floor(10 ** rng.uniform(0, np.log10(3000))))
+        kind = KINDS[int(rng.integers(0, 4))]
+        q = datagen.uniform_cube(m, 100 + i) if t == 0 else datagen.uniform_cube(m, 100 + i, -1.0, 1.0)
+        reqs.append(dict(tree=t, kind=kind, q=q, radius=0.03 if t == 0 else 0.02))
+    return [cube, shell], trees, reqs
+
+
+def _submit(s, tids, r):
+    if r["kind"] == "radius":
+        return s.submit(tids[r["tree"]], abx.REQ_RADIUS, r["q"], radius=r["radius"])
+    return s.submit(tids[r["tree"]], abx.REQ_NEAREST, r["q"], k=r["kind"])
+
+
+def _rows(res):
+    o, i = res["offsets"], res["indices"]
+    return [tuple(sorted(i[o[j]:o[j + 1]].tolist())) for j in range(len(o) - 1)]
+
+
+def test_serving_results_alone_equal_mix(orc):
+    prims, trees, reqs = _setup()
+    alone = []
+    s1 = abx.Server(slots=1, budget_bytes=256 << 20, host_bytes=256 << 20)
+    t1 = [s1.add_tree(t) for t in trees]
+    for r in reqs:
+        tk = _submit(s1, t1, r)
+        alone.append(s1.wait(tk))
+        s1.release(tk)
+    s1.close()
+    # four slots and a budget of a few requests: admission back-pressure
+    s4 = abx.Server(slots=4, budget_bytes=2 << 20, host_bytes=256 << 20)
+    t4 = [s4.add_tree(t) for t in trees]
+    tickets = [_submit(s4, t4, r) for r in reqs]
+    mix = [s4.wait(t) for t in tickets]
+    st = s4.stats()
+    s4.close()
+    assert st["completed"] == len(reqs) and st["device_high_water"] <= 2 << 20
+    for r, a, b in zip(reqs, alone, mix):
+        assert a["status"] == abx.OK and b["status"] == abx.OK
+        assert np.array_equal(a["offsets"], b["offsets"])
+        if r["kind"] == "radius":
+            assert _rows(a) == _rows(b)
+        else:
+            assert np.array_equal(a["indices"], b["indices"])
+            assert np.array_equal(a["distances"], b["distances"])
+        assert a["t_arrival"] <= a["t_admit"] <= a["t_done"]
+    # oracle parity on every request (rows sampled in the larger ones)
+    for r, b in zip(reqs, mix):
+        p = prims[r["tree"]]
+        m = len(r["q"])
+        rows = np.unique(np.linspace(0, m - 1, min(m, 40)).astype(np.int64))
+        if r["kind"] == "radius":
+            check_spatial(orc, p, 0, r["q"], orc.WITHIN, b["offsets"], b["indices"],
+                          radius=r["radius"], rows=rows)
+        else:
+            k = r["kind"]
+            check_nearest(orc, p, 0, r["q"], k, b["indices"].reshape(m, k), b["distances"].reshape(m, k),
+                          rows=rows)
+
+
+def test_serving_capacity_error_does_not_block():
+    cube = datagen.uniform_cube(5000, 1)
+    t = abx.bvh_build(torch.from_numpy(cube).cuda())
+    s = abx.Server(slots=2, budget_bytes=1 << 20, host_bytes=64 << 20)
+    tid = s.add_tree(t)
+    small = datagen.uniform_cube(100, 2)
+    big = datagen.uniform_cube(200_000, 3)
+    a = s.submit(tid, abx.REQ_NEAREST, small, k=4)
+    b = s.submit(tid, abx.REQ_NEAREST, big, k=32)       # reservation > budget
+    c = s.submit(tid, abx.REQ_RADIUS, small, radius=0.05)
+    assert s.wait(a)["status"] == abx.OK
+    assert s.wait(b)["status"] == abx.ERR_CAPACITY
+    assert s.wait(c)["status"] == abx.OK
+    s.close()
