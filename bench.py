@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3"])
+    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C4", "C5", "COPY"])
     ap.add_argument("--nodes", default="q16", choices=["fp32", "q16"])
     ap.add_argument("--morton-bits", type=int, default=21)
     ap.add_argument("--k", type=int, default=10)
@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--compare-formats", action="store_true",
                     help="also measure the other node format's query rates (untimed block)")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests per load level of the serving block (0: skip it)")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
+    ap.add_argument("--trees", type=int, default=256, help="forest size (C4)")
     return ap.parse_args()
 
 
@@ -62,6 +66,22 @@ def main():
     from paper_1908_11807_amd import abx, datagen
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.workload == "C4":
+        print(json.dumps(bench_forest(args)), flush=True)
+        return
+    if args.workload == "C5":
+        print(json.dumps(bench_serving(args, standalone=True)), flush=True)
+        return
+    if args.workload == "COPY":
+        # plain 1 GiB device copy: the reference for scaling HBM counters
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(max(args.steps, 1)):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"metric": "device copy", "bytes_read_per_copy": x.numel() * 4,
+                          "bytes_written_per_copy": x.numel() * 4, "copies": max(args.steps, 1)}))
+        return
     dev = torch.device("cuda:0")
     cfg = datagen.CONFIGS[args.workload]
     pts_np, q_np = datagen.config_inputs(args.workload)
@@ -106,13 +126,20 @@ def main():
     step_ms = phases.sum(axis=1)
     build_ms, rad_ms, knn_ms = np.median(phases, axis=0)
 
-    kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "quantise", "scene_partial",
-               "query_codes", "spatial_count", "spatial_fill", "scan_tiles", "nearest"]
+    kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_top", "quantise",
+               "scene_partial", "query_codes", "spatial_count", "spatial_fill", "scan_tiles", "nearest",
+               "nearest_coop"]
     ktimes = {}
     for name in kernels:
         ms, cnt = abx.timing_get(name)
         if cnt:
             ktimes[name] = dict(ms_per_launch=ms / cnt, launches_per_step=cnt / args.steps)
+    # the nearest traversal is two launches (one lane per query, then one
+    # wavefront per heavy query); the roofline takes them together
+    if "nearest" in ktimes and "nearest_coop" in ktimes:
+        ktimes["nearest+coop"] = dict(
+            ms_per_launch=ktimes["nearest"]["ms_per_launch"] + ktimes["nearest_coop"]["ms_per_launch"],
+            launches_per_step=1.0)
 
     # dominant kernel and its algorithmic bytes per launch
     node_b = 32 if args.nodes == "q16" else 64
@@ -122,13 +149,14 @@ def main():
     hits = total_hits
     alg = {
         # query point 12 B + order 4 B + k' results (index 4 B + distance 4 B)
-        "nearest": algorithmic_bytes(st_knn, node_b, leaf_b, 16 + 8 * min(k, n)),
+        "nearest+coop": algorithmic_bytes(st_knn, node_b, leaf_b, 16 + 8 * min(k, n)),
         # query 12 B + order 4 B + count write 4 B
         "spatial_count": algorithmic_bytes(st_sp, node_b, leaf_b, 20),
         # query 12 B + order 4 B + offsets 8 B, plus 4 B per written index
         "spatial_fill": algorithmic_bytes(st_sp, node_b, leaf_b, 24) + 4 * hits,
     }
-    dom = max((kname for kname in ktimes), key=lambda kn: ktimes[kn]["ms_per_launch"] * ktimes[kn]["launches_per_step"])
+    dom = max((kn for kn in ktimes if kn not in ("nearest", "nearest_coop")),
+              key=lambda kn: ktimes[kn]["ms_per_launch"] * ktimes[kn]["launches_per_step"])
     if dom in alg:
         per_launch = alg[dom]
         achieved = per_launch / (ktimes[dom]["ms_per_launch"] * 1e-3) / 1e9
@@ -182,7 +210,178 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pts_np, q_np, r, k, args.cpu_seconds)
 
+    if args.serve_requests > 0 and args.workload == "C3":
+        del t, off, idx, ki, kd
+        torch.cuda.empty_cache()
+        out["serving"] = bench_serving(args, standalone=False)
+        out["p99_batch_latency_ms"] = out["serving"]["loads"][-1]["p99_ms"]
+
     print(json.dumps(out), flush=True)
+
+
+def forest_inputs(n_trees, seed=401):
+    """256 trees, sizes log-uniform in [1e3, 1e6]; even ids uniform cube, odd
+    ids Gaussian clusters; each tree's queries from its own distribution."""
+    from paper_1908_11807_amd import datagen
+    sizes = datagen.forest_sizes(n_trees, seed)
+    pts, qs = [], []
+    for t, n in enumerate(sizes):
+        p, q = datagen.forest_tree(t, int(n), seed)
+        pts.append(p)
+        qs.append(q)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return np.concatenate(pts), off, np.concatenate(qs), off.copy()
+
+
+def bench_forest(args):
+    import torch
+    from paper_1908_11807_amd import abx
+    k = 16
+    pts_np, off, q_np, qoff = forest_inputs(args.trees)
+    N, M = int(off[-1]), int(qoff[-1])
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        pts = torch.from_numpy(pts_np).cuda()
+        qs = torch.from_numpy(q_np).cuda()
+        plan = abx.ForestPlan(pts, off, qs, qoff, k, node_format=args.nodes)
+        plan.check()
+        tuned = plan.autotune()
+        plan.capture(build=True)
+        for _ in range(max(args.warmup, 1)):
+            plan.replay()
+        torch.cuda.synchronize()
+        abx.timing_reset()
+        # per-kernel times of one eager step with events (graph replays carry none)
+        abx.timing_enable(True)
+        plan.build()
+        plan.query()
+        torch.cuda.synchronize()
+        abx.timing_enable(False)
+        ktimes = {}
+        for name in ("forest_nearest", "forest_nearest_coop", "refit", "sort_onesweep", "karras",
+                     "forest_keys", "forest_qkeys"):
+            ms, cnt = abx.timing_get(name)
+            if cnt:
+                ktimes[name] = round(ms, 4)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev[0].elapsed_time(ev[1]) / args.steps
+    return {
+        "metric": "forest kNN queries/s (k=16, build + query per step, one HIP graph)",
+        "value": round(M / (ms * 1e-3), 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "wall_ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"C4: forest of {args.trees} trees, sizes log-uniform [1e3,1e6], "
+                               "uniform cube / Gaussian clusters, equal-count queries",
+                   "trees": args.trees, "points": N, "queries": M, "k": k, "nodes": args.nodes,
+                   "tuned": tuned},
+        "eager_kernel_ms": ktimes,
+        "results": plan.total,
+    }
+
+
+def bench_serving(args, standalone):
+    """4 device-resident trees of 1e7 points (two uniform cubes, two thin
+    shells); Poisson stream of requests (m = floor(10^U(0,5)), kind radius /
+    k=1 / k=8 / k=32, tree uniform); saturated throughput, then p50/p99
+    latency at fractions of it."""
+    import torch
+    from paper_1908_11807_amd import abx, datagen
+    n = 10_000_000
+    dev = torch.device("cuda:0")
+    trees, radii, pools = [], [], []
+    for t in range(4):
+        if t < 2:
+            p = datagen.uniform_cube(n, 501 + t)
+            radii.append(float(np.float32(datagen.radius_for_density(n))))
+            pools.append(torch.from_numpy(datagen.uniform_cube(1_000_000, 601 + t)).pin_memory())
+        else:
+            p = datagen.shell(n, 501 + t)
+            radii.append(float(np.float32(datagen.radius_for_shell(n, 1e-3))))
+            pools.append(torch.from_numpy(datagen.uniform_cube(1_000_000, 601 + t, -1.0, 1.0)).pin_memory())
+        trees.append(abx.bvh_build(torch.from_numpy(p).to(dev), node_format=args.nodes))
+        del p
+    torch.cuda.synchronize()
+    budget = 2 << 30
+    srv = abx.Server(slots=4, budget_bytes=budget, host_bytes=2 << 30)
+    tids = [srv.add_tree(t) for t in trees]
+    kinds = ("radius", 1, 8, 32)
+
+    def make(nreq, seed, rate):
+        reqs = datagen.request_stream(nreq, seed, rate, 4, kinds=kinds)
+        rng = np.random.default_rng(seed + 1)
+        for r in reqs:
+            o = int(rng.integers(0, 1_000_000 - r["m"] + 1))
+            r["q"] = pools[r["tree"]][o:o + r["m"]]
+        return reqs
+
+    def run(reqs, t0, paced):
+        lat, done, live = [], 0, {}
+        qsum = 0
+        last = t0
+        for r in reqs:
+            ta = t0 + r["t_arrival"] if paced else t0
+            if paced:
+                while abx.server_now() < ta:
+                    for tk in list(live):
+                        res = srv.poll(tk, copy=False)
+                        if res is not None:
+                            lat.append(res["t_done"] - res["t_arrival"])
+                            last = max(last, res["t_done"])
+                            srv.release(tk)
+                            del live[tk]
+            kind = r["kind"]
+            if kind == "radius":
+                tk = srv.submit(tids[r["tree"]], abx.REQ_RADIUS, r["q"], radius=radii[r["tree"]], t_arrival=ta)
+            else:
+                tk = srv.submit(tids[r["tree"]], abx.REQ_NEAREST, r["q"], k=kind, t_arrival=ta)
+            live[tk] = r
+            qsum += r["m"]
+        for tk in list(live):
+            res = srv.wait(tk, copy=False)
+            lat.append(res["t_done"] - res["t_arrival"])
+            last = max(last, res["t_done"])
+            srv.release(tk)
+        return np.array(lat), qsum, last - t0
+
+    nreq = max(args.serve_requests, 20)
+    run(make(min(nreq, 100), 700, 1.0), abx.server_now(), paced=False)   # warm-up
+    lat, qsum, span = run(make(nreq, 701, 1.0), abx.server_now(), paced=False)
+    sat_rps = nreq / span
+    out = {"saturated_requests_per_s": round(sat_rps, 1), "saturated_queries_per_s": round(qsum / span, 1),
+           "loads": []}
+    for i, f in enumerate(float(x) for x in args.serve_loads.split(",")):
+        reqs = make(nreq, 710 + i, f * sat_rps)
+        lat, qsum, span = run(reqs, abx.server_now() + 0.01, paced=True)
+        out["loads"].append({"offered": f, "requests_per_s": round(nreq / span, 1),
+                             "queries_per_s": round(qsum / span, 1),
+                             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3)})
+    st = srv.stats()
+    out["server"] = {"slots": 4, "budget_bytes": budget, "max_in_flight": st["max_in_flight"],
+                     "device_high_water": st["device_high_water"], "failed": st["failed"]}
+    out["requests_per_level"] = nreq
+    srv.close()
+    if standalone:
+        top = out["loads"][-1]
+        return {"metric": "serving p99 batch latency at 95% load (4 x 1e7-point trees)",
+                "value": top["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": nreq, "warmup": 100,
+                "ms_per_step": top["p50_ms"], "higher_is_better": False, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                "config": {"workload": "C5: 4 device-resident trees of 1e7 points (2 cube, 2 shell), "
+                                       "Poisson requests m=floor(10^U(0,5)), radius/k=1/8/32, "
+                                       "HBM budget 2 GiB", "nodes": args.nodes},
+                "serving": out}
+    return out
 
 
 def cpu_baseline(pts, q, r, k, budget_s):

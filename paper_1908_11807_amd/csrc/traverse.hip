@@ -21,6 +21,8 @@
 // lane, so a wavefront's pushes hit distinct banks); deeper entries spill
 // to the lane's private memory.  Trees deeper than kMaxDepth are refused on
 // the host.
+#include <algorithm>
+
 #include "traverse_common.h"
 
 namespace abx {
@@ -294,12 +296,20 @@ abx_status nearest_fmt(const abx_bvh *b, const float *pts, int64_t m, const int3
   return nearest_k<KIND, FMT, 32>(b, pts, m, order, k, idx, dist, stats, ns, s);
 }
 
+// Small batches leave most of the GPU idle, so their heavy queries are
+// better served early by whole wavefronts: the one-lane budget shrinks with
+// the batch (never below 512 visits, never above the configured budget).
+int64_t effective_budget(int64_t budget, int64_t m) {
+  const int64_t b = std::max<int64_t>(512, m / 16);
+  return std::min(budget, b);
+}
+
 abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order,
                           int k, int32_t *idx, float *dist, int32_t *stats, int32_t *heavy_q,
                           float *heavy_bound, uint32_t *counters, int64_t budget, hipStream_t s) {
   if (m == 0 || k == 0) return ABX_OK;
   if (k > 32) return ABX_ERR_UNSUPPORTED;
-  const NearestScratch ns{heavy_q, heavy_bound, counters, budget};
+  const NearestScratch ns{heavy_q, heavy_bound, counters, effective_budget(budget, m)};
   if (b->kind == ABX_PRIM_POINTS) {
     if (b->format == ABX_NODES_FP32)
       return nearest_fmt<ABX_PRIM_POINTS, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, ns, s);
