@@ -142,8 +142,8 @@ def main():
             launches_per_step=1.0)
 
     # dominant kernel and its algorithmic bytes per launch
-    node_b = 32 if args.nodes == "q16" else 64
-    leaf_b = 16 if args.nodes == "q16" else 4
+    node_b = int(t.layout.node_bytes)
+    leaf_b = int(t.layout.leaf_bytes)
     st_knn = abx.query_nearest_stats(t, qs, k).cpu().numpy()
     st_sp = abx.query_spatial_stats(t, qs, radius=r).cpu().numpy()
     hits = total_hits

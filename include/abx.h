@@ -63,13 +63,16 @@ typedef enum {
 
 /* Storage of the internal nodes.
  *   FP32: 64 B per internal node -- both children's float32 boxes and
- *         their references; leaves store only the permutation index.
- *   Q16 : 32 B per internal node -- children's boxes quantised to 16 bits
- *         per coordinate on the scene box's grid, rounded outward so every
- *         quantised box contains the exact one; leaves keep the exact
- *         float32 primitive box, so results are identical to FP32.  (The
- *         paper names quantised bounds as a way to cut BVH bandwidth,
- *         section 2 literature review.) */
+ *         their references.  A leaf child's box is its primitive's exact
+ *         box and its reference names the primitive, so traversal reads
+ *         nothing else.
+ *   Q16 : 32 B per internal node -- internal children's boxes quantised to
+ *         16 bits per coordinate on the scene box's grid, rounded outward
+ *         so every quantised box contains the exact one.  In point trees a
+ *         leaf child's slot holds the point's float32 coordinates; box
+ *         trees keep the exact float32 box in a leaf record.  Results are
+ *         identical to FP32.  (The paper names quantised bounds as a way to
+ *         cut BVH bandwidth, section 2 literature review.) */
 typedef enum { ABX_NODES_FP32 = 0, ABX_NODES_Q16 = 1 } abx_node_format;
 
 typedef struct {
@@ -113,8 +116,10 @@ typedef struct {
   size_t nodes_offset;    /* byte offset of internal node 0 in tree memory */
   size_t node_bytes;      /* 64 (FP32) or 32 (Q16)                          */
   size_t leaves_offset;   /* byte offset of leaf 0                          */
-  size_t leaf_bytes;      /* 4 (FP32: int32 permutation index) or 16/32 (Q16:
-                             float xyz + int32 index / float lo,hi + index)  */
+  size_t leaf_bytes;      /* 4: int32 permutation, sorted position ->
+                             primitive index (FP32, and Q16 point trees);
+                             32: Q16 box trees, record i = primitive i's
+                             float lo xyz, hi xyz, its sorted position, pad */
   float q16_origin[3];    /* Q16 dequantisation: x = fmaf(q, scale, origin) */
   float q16_scale[3];
 } abx_bvh_layout;

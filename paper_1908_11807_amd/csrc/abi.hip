@@ -26,7 +26,7 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
                         TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
                         uint32_t *frontier_count, hipStream_t s);
 size_t refit_frontier_cap(int64_t n);
-abx_status launch_quantise(const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
+abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
                            hipStream_t s);
 // traverse.hip
 abx_status launch_query_codes(const abx_bvh *b, const float *q, int64_t m, int width,
@@ -74,6 +74,7 @@ abx_status row_offsets(int32_t *off, int64_t m, int32_t k, hipStream_t s) {
 struct BuildLayout {
   int64_t n, ni;
   bool wide, q16;
+  bool boxrec;  // Q16 box tree: exact box records in the leaf region
   int bits;
   size_t node_bytes, leaf_bytes;
   size_t nodes_off, leaves_off, tree_total;
@@ -105,7 +106,8 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   L.wide = L.bits > 10;
   L.q16 = o && o->node_format == ABX_NODES_Q16;
   L.node_bytes = L.q16 ? sizeof(NodeQ16) : sizeof(NodeF32);
-  L.leaf_bytes = L.q16 ? (p->kind == ABX_PRIM_POINTS ? 16 : 32) : 4;
+  L.boxrec = L.q16 && p->kind == ABX_PRIM_BOXES;
+  L.leaf_bytes = L.boxrec ? 32 : 4;
   size_t off = sizeof(TreeHeader);
   L.nodes_off = off;
   off = align_up(off + (size_t)L.ni * L.node_bytes, 256);
@@ -123,7 +125,7 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   L.sorted = off;
   off = align_up(off + n * ksz, 256);
   L.perm = off;
-  off = align_up(off + (L.q16 ? n * 4 : 0), 256);
+  off = align_up(off + (L.boxrec ? n * 4 : 0), 256);
   L.parent_leaf = off;
   off = align_up(off + n * 4, 256);
   L.parent_int = off;
@@ -357,8 +359,8 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
 
   const int blocks = scene_blocks(n);
   ABX_TRY(launch_scene(kind, prims->data, n, reinterpret_cast<float *>(sc + L.partial), blocks, hdr, s));
-  int32_t *perm = L.q16 ? reinterpret_cast<int32_t *>(sc + L.perm)
-                        : reinterpret_cast<int32_t *>(tree + L.leaves_off);
+  int32_t *perm = L.boxrec ? reinterpret_cast<int32_t *>(sc + L.perm)
+                           : reinterpret_cast<int32_t *>(tree + L.leaves_off);
   NodeF32 *fnodes = L.q16 ? reinterpret_cast<NodeF32 *>(sc + L.staging)
                           : reinterpret_cast<NodeF32 *>(tree + L.nodes_off);
   int32_t *parent_leaf = reinterpret_cast<int32_t *>(sc + L.parent_leaf);
@@ -376,7 +378,7 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
     ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, parent_leaf, parent_int, other_end,
                          fnodes, flags, hdr, tree + L.leaves_off, frontier, fcount, s));
     if (L.q16)
-      ABX_TRY(launch_quantise(fnodes, L.ni, hdr, reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
+      ABX_TRY(launch_quantise(kind, fnodes, L.ni, hdr, reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
   }
   TreeHeader h;
   ABX_HIP(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));

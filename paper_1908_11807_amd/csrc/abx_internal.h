@@ -16,11 +16,14 @@ constexpr int kWave = 64;
 // Tree memory (caller-owned, one buffer):
 //   [0, 256)                 TreeHeader
 //   [nodes_off, +(n-1)*NB)   internal nodes, NB = 64 (FP32) or 32 (Q16)
-//   [leaves_off, +n*LB)      leaves: FP32 -> int32 permutation index (LB=4);
-//                            Q16 points -> float4 {x,y,z,idx} (LB=16);
-//                            Q16 boxes  -> {lo xyz, hi xyz, idx, pad} (LB=32)
-// Child references: r >= 0 is internal node r, r < 0 is the leaf at sorted
-// position ~r.  Internal node 0 is the root (Karras numbering).
+//   [leaves_off, +n*LB)      FP32 and Q16 point trees: int32 permutation,
+//                            sorted position -> primitive index (LB=4);
+//                            Q16 box trees: record i = primitive i's exact
+//                            {lo xyz, hi xyz, sorted position, pad} (LB=32)
+// Child references: r >= 0 is internal node r, r < 0 is a leaf holding
+// primitive ~r (the hierarchy numbers leaves by sorted position; the refit
+// rewrites leaf references to name the primitive, so traversal needs no
+// permutation lookup).  Internal node 0 is the root (Karras numbering).
 // ---------------------------------------------------------------------------
 struct TreeHeader {
   float scene[6];     // scene box lo xyz, hi xyz
@@ -46,7 +49,8 @@ static_assert(sizeof(NodeF32) == 64, "fp32 node is 64 B");
 
 // Q16 internal node, 32 B: 12 uint16 coordinates then the two references
 //   w[0..5] = L.lo.xy | L.lo.z L.hi.x | L.hi.yz | R.lo.xy | R.lo.z R.hi.x | R.hi.yz
-//   (low half first), w[6] = left ref, w[7] = right ref
+//   (low half first), w[6] = left ref, w[7] = right ref.  In a point tree
+//   a leaf child's three words hold the point's float32 x, y, z instead.
 struct __align__(16) NodeQ16 {
   uint4 a, b;
 };

@@ -235,7 +235,9 @@ __device__ __forceinline__ void load_child(const NodeF32 *node, int side, float 
 // Bottom-up refit in two launches.  One thread per leaf climbs from its
 // leaf: at each parent it writes its box into its child slot, then counts
 // its arrival; the first arrival stops, the second unions both children and
-// climbs on.  For Q16 trees the leaf record is written here too.
+// climbs on.  The leaf's thread also rewrites its parent's reference to the
+// leaf from the sorted position to ~(primitive index), and for Q16 box trees
+// writes the exact box record.
 //
 // Phase 1: each workgroup owns a chunk of kRefitChunk consecutive leaves (in
 // sorted order).  An internal node whose leaf range lies inside the chunk has
@@ -273,19 +275,17 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_local(
       b[a] = KIND == ABX_PRIM_POINTS ? prims[3 * (int64_t)orig + a] : prims[6 * (int64_t)orig + a];
       b[3 + a] = KIND == ABX_PRIM_POINTS ? b[a] : prims[6 * (int64_t)orig + 3 + a];
     }
-    if (kQ16) {
-      if (KIND == ABX_PRIM_POINTS) {
-        reinterpret_cast<float4 *>(q16_leaves)[p] =
-            make_float4(b[0], b[1], b[2], __int_as_float(orig));
-      } else {
-        float4 *o = reinterpret_cast<float4 *>(q16_leaves) + 2 * p;
-        o[0] = make_float4(b[0], b[1], b[2], b[3]);
-        o[1] = make_float4(b[4], b[5], __int_as_float(orig), 0.0f);
-      }
+    if (kQ16 && KIND == ABX_PRIM_BOXES) {
+      // exact box record of a Q16 box tree, addressed by primitive index
+      float4 *o = reinterpret_cast<float4 *>(q16_leaves) + 2 * (int64_t)orig;
+      o[0] = make_float4(b[0], b[1], b[2], b[3]);
+      o[1] = make_float4(b[4], b[5], __int_as_float((int32_t)p), 0.0f);
     }
     if (n == 1) return;
     int h = 0;
     int32_t pp = parent_leaf[p];
+    // the parent's reference to this leaf names the primitive itself
+    reinterpret_cast<int32_t *>(nodes + (pp >> 1))[12 + (pp & 1)] = ~orig;
     for (int step = 0; step < kRefitMaxSteps; ++step) {
       const int32_t parent = pp >> 1, side = pp & 1;
       store_child(nodes + parent, side, b, h);
@@ -385,6 +385,11 @@ __device__ __forceinline__ uint32_t q_hi(float x, float o, float s) {
   return q;
 }
 
+// Q16 node from the FP32 one.  Internal children get outward-rounded 16-bit
+// boxes; in a point tree a leaf child's 12-byte slot holds the point's
+// float32 x, y, z instead (the traversal tells the two apart by the sign of
+// the reference), so point leaves need no second memory access.
+template <int KIND>
 __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restrict__ src,
                                                           int64_t ni,
                                                           const TreeHeader *__restrict__ hdr,
@@ -393,20 +398,28 @@ __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restr
   if (i >= ni) return;
   const float *f = reinterpret_cast<const float *>(src + i);
   const int4 d = src[i].d;
-  uint32_t q[12];
+  uint32_t w[6];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
+    const bool leaf = (c == 0 ? d.x : d.y) < 0;
+    if (KIND == ABX_PRIM_POINTS && leaf) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float o = hdr->q_origin[a], s = hdr->q_scale[a];
-      q[6 * c + a] = q_lo(f[6 * c + a], o, s);
-      q[6 * c + 3 + a] = q_hi(f[6 * c + 3 + a], o, s);
+      for (int a = 0; a < 3; ++a) w[3 * c + a] = __float_as_uint(f[6 * c + a]);
+    } else {
+      uint32_t q[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float o = hdr->q_origin[a], sc = hdr->q_scale[a];
+        q[a] = q_lo(f[6 * c + a], o, sc);
+        q[3 + a] = q_hi(f[6 * c + 3 + a], o, sc);
+      }
+#pragma unroll
+      for (int h = 0; h < 3; ++h) w[3 * c + h] = q[2 * h] | (q[2 * h + 1] << 16);
     }
   }
   NodeQ16 out;
-  out.a = make_uint4(q[0] | (q[1] << 16), q[2] | (q[3] << 16), q[4] | (q[5] << 16),
-                     q[6] | (q[7] << 16));
-  out.b = make_uint4(q[8] | (q[9] << 16), q[10] | (q[11] << 16), (uint32_t)d.x, (uint32_t)d.y);
+  out.a = make_uint4(w[0], w[1], w[2], w[3]);
+  out.b = make_uint4(w[4], w[5], (uint32_t)d.x, (uint32_t)d.y);
   dst[i] = out;
 }
 
@@ -499,11 +512,16 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
   });
 }
 
-abx_status launch_quantise(const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
-                           hipStream_t s) {
+abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, const TreeHeader *hdr,
+                           NodeQ16 *dst, hipStream_t s) {
   if (ni <= 0) return ABX_OK;
+  const unsigned g = grid_for(ni, kBuildBlock);
+  if (kind == ABX_PRIM_POINTS)
+    return launch("quantise", s, [&] {
+      k_quantise<ABX_PRIM_POINTS><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, dst);
+    });
   return launch("quantise", s, [&] {
-    k_quantise<<<grid_for(ni, kBuildBlock), kBuildBlock, 0, s>>>(src, ni, hdr, dst);
+    k_quantise<ABX_PRIM_BOXES><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, dst);
   });
 }
 

@@ -180,15 +180,17 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_keys(const float *__res
   keys[i] = ((uint64_t)t << kForestKeyShift) | code;
 }
 
-// root of each tree: the hierarchy node whose range is the tree's run
+// root of each tree: the hierarchy node whose range is the tree's run, or
+// ~(primitive index) for a one-point tree
 __global__ void k_forest_roots(const int64_t *__restrict__ off, int T,
-                               const int32_t *__restrict__ other_end, int32_t *__restrict__ roots) {
+                               const int32_t *__restrict__ other_end,
+                               const int32_t *__restrict__ perm, int32_t *__restrict__ roots) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
   const int64_t f = off[t], l = off[t + 1] - 1;
   int32_t r;
-  if (l < f) r = INT32_MIN;          // empty tree
-  else if (l == f) r = ~(int32_t)f;  // one leaf
+  if (l < f) r = INT32_MIN;        // empty tree
+  else if (l == f) r = ~perm[f];   // one leaf
   else r = other_end[f] == l ? (int32_t)f : (int32_t)l;
   roots[t] = r;
 }
@@ -260,10 +262,15 @@ struct ForestMap {
   }
 };
 
+// occupancy target: the persistent loop keeps a few more values live than
+// the plain pass
+constexpr int forest_waves_per_eu(int K) { return K > 16 ? 2 : (K > 10 ? 4 : (K > 4 ? 6 : 8)); }
+
 // Persistent pass 1 over every tree's queries: each wavefront takes
 // `grab` tiles of 64 Morton-ordered queries at a time from the queue.
 template <int KIND, int FMT, int K>
-__global__ __launch_bounds__(kForestBlock) void k_forest_nearest(TreeArgs t, ForestMap map,
+__global__ __launch_bounds__(kForestBlock)
+__attribute__((amdgpu_waves_per_eu(forest_waves_per_eu(K)))) void k_forest_nearest(TreeArgs t, ForestMap map,
                                                                  const float *__restrict__ pts,
                                                                  int64_t M, const int32_t *__restrict__ order,
                                                                  int32_t *__restrict__ indices,
@@ -316,10 +323,10 @@ abx_status forest_launch_build(const float *pts, int64_t N, const int64_t *off_d
   });
 }
 
-abx_status forest_launch_roots(const int64_t *off, int T, const int32_t *other_end, int32_t *roots,
-                               hipStream_t s) {
+abx_status forest_launch_roots(const int64_t *off, int T, const int32_t *other_end, const int32_t *perm,
+                               int32_t *roots, hipStream_t s) {
   return launch("forest_roots", s, [&] {
-    k_forest_roots<<<grid_for(T, 256), 256, 0, s>>>(off, T, other_end, roots);
+    k_forest_roots<<<grid_for(T, 256), 256, 0, s>>>(off, T, other_end, perm, roots);
   });
 }
 

@@ -17,8 +17,8 @@ size_t forest_tree_extra(int T);
 abx_status forest_launch_build(const float *pts, int64_t N, const int64_t *off_dev, int T,
                                int32_t *tbox, float *tscene, int64_t *off_copy, TreeHeader *hdr,
                                uint64_t *keys, hipStream_t s);
-abx_status forest_launch_roots(const int64_t *off, int T, const int32_t *other_end, int32_t *roots,
-                               hipStream_t s);
+abx_status forest_launch_roots(const int64_t *off, int T, const int32_t *other_end, const int32_t *perm,
+                               int32_t *roots, hipStream_t s);
 abx_status forest_launch_qkeys(const float *q, int64_t M, const int64_t *qoff, int T, const float *tscene,
                                uint64_t *keys, int32_t *qtree, hipStream_t s);
 abx_status forest_launch_rows(const int64_t *poff, const int64_t *qoff, const int32_t *qtree, int64_t M,
@@ -38,7 +38,7 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
                         const int32_t *other_end, NodeF32 *nodes, uint32_t *flags,
                         TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
                         uint32_t *frontier_count, hipStream_t s);
-abx_status launch_quantise(const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
+abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
                            hipStream_t s);
 size_t refit_frontier_cap(int64_t n);
 int max_tree_depth();
@@ -57,7 +57,7 @@ struct ForestLayout {
   bool q16;
   size_t node_bytes, leaf_bytes;
   size_t nodes, leaves, roots, tscene, offs, tree_total;
-  size_t tbox, keys, sorted, perm, parent_leaf, parent_int, other_end, flags, frontier, staging, sort,
+  size_t tbox, keys, sorted, parent_leaf, parent_int, other_end, flags, frontier, staging, sort,
       scratch_total;
 };
 
@@ -68,7 +68,7 @@ ForestLayout forest_layout(int T, int64_t N, bool q16) {
   L.ni = N > 1 ? N - 1 : 0;
   L.q16 = q16;
   L.node_bytes = q16 ? sizeof(NodeQ16) : sizeof(NodeF32);
-  L.leaf_bytes = q16 ? 16 : 4;
+  L.leaf_bytes = 4;
   size_t off = sizeof(TreeHeader);
   L.nodes = off;
   off = align_up(off + (size_t)L.ni * L.node_bytes, 256);
@@ -89,8 +89,6 @@ ForestLayout forest_layout(int T, int64_t N, bool q16) {
   off = align_up(off + n * 8, 256);
   L.sorted = off;
   off = align_up(off + n * 8, 256);
-  L.perm = off;
-  off = align_up(off + (q16 ? n * 4 : 0), 256);
   L.parent_leaf = off;
   off = align_up(off + n * 4, 256);
   L.parent_int = off;
@@ -241,8 +239,7 @@ abx_status abx_forest_build(const abx_forest_primitives *prims, void *tree_mem, 
   ABX_TRY(forest_launch_build(prims->data, N, prims->offsets_dev, T, reinterpret_cast<int32_t *>(sc + L.tbox),
                               tscene, offs, hdr, reinterpret_cast<uint64_t *>(sc + L.keys), s));
   if (N > 0) {
-    int32_t *perm = q16 ? reinterpret_cast<int32_t *>(sc + L.perm)
-                        : reinterpret_cast<int32_t *>(tree + L.leaves);
+    int32_t *perm = reinterpret_cast<int32_t *>(tree + L.leaves);
     NodeF32 *fnodes = q16 ? reinterpret_cast<NodeF32 *>(sc + L.staging)
                           : reinterpret_cast<NodeF32 *>(tree + L.nodes);
     int32_t *parent_leaf = reinterpret_cast<int32_t *>(sc + L.parent_leaf);
@@ -256,9 +253,10 @@ abx_status abx_forest_build(const abx_forest_primitives *prims, void *tree_mem, 
                          reinterpret_cast<int32_t *>(sc + L.frontier + 256),
                          reinterpret_cast<uint32_t *>(sc + L.frontier), s));
     if (q16)
-      ABX_TRY(launch_quantise(fnodes, L.ni, hdr, reinterpret_cast<NodeQ16 *>(tree + L.nodes), s));
+      ABX_TRY(launch_quantise(ABX_PRIM_POINTS, fnodes, L.ni, hdr, reinterpret_cast<NodeQ16 *>(tree + L.nodes), s));
   }
-  ABX_TRY(forest_launch_roots(offs, T, other_end, roots, s));
+  ABX_TRY(forest_launch_roots(offs, T, other_end, reinterpret_cast<const int32_t *>(tree + L.leaves),
+                              roots, s));
 
   abx_forest *f = new (std::nothrow) abx_forest;
   if (!f) return ABX_ERR_INVALID_ARG;
@@ -344,7 +342,7 @@ abx_status abx_forest_autotune(abx_forest *f, const abx_forest_queries *q, int32
   if (!f || !best) return ABX_ERR_INVALID_ARG;
   if (graph_capturing()) return ABX_ERR_INVALID_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int bpcs[] = {2, 4, 5};
+  const int bpcs[] = {2, 4, 6, 8};
   const int grabs[] = {1, 4};
   const int64_t budgets[] = {4096, 16384, 65536};
   hipEvent_t a, b;

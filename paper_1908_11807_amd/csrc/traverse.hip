@@ -17,10 +17,10 @@
 // candidates cannot improve the result.  The k best candidates are kept
 // sorted in registers by (squared distance, index).
 //
-// Stack: the first kLdsDepth entries of each lane live in LDS (column per
-// lane, so a wavefront's pushes hit distinct banks); deeper entries spill
-// to the lane's private memory.  Trees deeper than kMaxDepth are refused on
-// the host.
+// Stack: the top entries of each lane live in a circular LDS window (column
+// per lane, so a wavefront's pushes hit distinct banks); deeper entries go to
+// the lane's private memory.  Trees deeper than kMaxDepth are refused on the
+// host.
 #include <algorithm>
 
 #include "traverse_common.h"
@@ -64,57 +64,49 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
   }
   int32_t *out = MODE == MODE_FILL ? indices + offsets[qi] : nullptr;
   const int32_t row_len = MODE == MODE_FILL ? offsets[qi + 1] - offsets[qi] : 0;
-  const int32_t *perm = reinterpret_cast<const int32_t *>(t.leaves);
   int32_t cnt = 0, visited = 0, leaf_reads = 0;
 
-  // a leaf child whose (node-stored) box passed: confirm and emit
-  auto leaf = [&](int32_t pos, const float *box) {
-    if (FMT == ABX_NODES_FP32) {
-      if (MODE == MODE_FILL && cnt < row_len) out[cnt] = perm[pos];
-      ++cnt;
-      if (MODE == MODE_STATS) ++leaf_reads;
-    } else {
+  // a leaf child (primitive idx) whose node-stored box passed: confirm where
+  // the slot is quantised, and emit
+  auto leaf = [&](int32_t idx) {
+    if (!exact_leaf_slots<KIND, FMT>()) {
       float b[6];
-      const int32_t idx = load_leaf_q16<KIND>(t, pos, b);
+      load_leaf_box(t, idx, b);
       if (MODE == MODE_STATS) ++leaf_reads;
-      if (q.test(b)) {
-        if (MODE == MODE_FILL && cnt < row_len) out[cnt] = idx;
-        ++cnt;
-      }
+      if (!q.test(b)) return;
     }
-    (void)box;
+    if (MODE == MODE_FILL && cnt < row_len) out[cnt] = idx;
+    ++cnt;
   };
 
   if (t.n == 1) {
-    if (FMT == ABX_NODES_FP32) {
-      if (q.test(t.scene)) leaf(0, t.scene);
-    } else {
-      leaf(0, t.scene);
-    }
+    // the scene box of a one-primitive tree is that primitive's box
+    if (q.test(t.scene)) leaf(0);
   } else {
-    int32_t ovf[kMaxDepth - kLdsDepthSpatial];
+    int32_t ovf[kMaxDepth];
     ABX_LDS int32_t *lds = (ABX_LDS int32_t *)(s_stack) + threadIdx.x;
-    int sp = 0;
+    int sp = 0, nl = 0;
     int32_t node = 0;
     // a tree has n-1 internal nodes, each visited at most once: the bound
     // only guarantees termination
     for (int64_t it = 0; it < t.n; ++it) {
       Kids k;
-      load_kids<FMT>(t, node, k);
+      load_kids<KIND, FMT>(t, node, k);
       if (MODE == MODE_STATS) ++visited;
       const bool hl = q.test(k.l), hr = q.test(k.r);
       const bool ll = k.lref < 0, lr = k.rref < 0;
-      if (hl && ll) leaf(~k.lref, k.l);
-      if (hr && lr) leaf(~k.rref, k.r);
+      if (hl && ll) leaf(~k.lref);
+      if (hr && lr) leaf(~k.rref);
       const bool gl = hl && !ll, gr = hr && !lr;
       if (gl) {
-        if (gr && sp < kMaxDepth) stack_push<int32_t, kLdsDepthSpatial, kTravBlock>(lds, ovf, sp, k.rref);
+        if (gr && sp < kMaxDepth)
+          stack_push<int32_t, kLdsDepthSpatial, kTravBlock>(lds, ovf, sp, nl, k.rref);
         node = k.lref;
       } else if (gr) {
         node = k.rref;
       } else {
         if (sp == 0) break;
-        node = stack_pop<int32_t, kLdsDepthSpatial, kTravBlock>(lds, ovf, sp);
+        node = stack_pop<int32_t, kLdsDepthSpatial, kTravBlock>(lds, ovf, sp, nl);
       }
     }
   }
@@ -128,7 +120,8 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
 // ------------------------------------------------------------------ nearest
 // Pass 1 over one tree: one lane per query, queries in Morton order.
 template <int KIND, int FMT, int K, bool STATS>
-__global__ __launch_bounds__(kTravBlock) void k_nearest(TreeArgs t, PlainMap map,
+__global__ __launch_bounds__(kTravBlock)
+__attribute__((amdgpu_waves_per_eu(nearest_waves_per_eu(K)))) void k_nearest(TreeArgs t, PlainMap map,
                                                         const float *__restrict__ pts, int64_t m,
                                                         const int32_t *__restrict__ order,
                                                         int32_t *__restrict__ indices,

@@ -12,7 +12,13 @@ namespace abx {
 constexpr int kTravBlock = 256;
 constexpr int kMaxDepth = 128;
 constexpr int kLdsDepthSpatial = 16;
-constexpr int kLdsDepthNearest = 16;
+constexpr int kLdsDepthNearest = 8;
+
+// Occupancy target of the one-lane nearest pass: 8 waves per SIMD fit the
+// register budget (64 VGPRs) up to k = 16; the k = 32 list alone takes 64.
+constexpr int nearest_waves_per_eu(int K) { return K > 16 ? 4 : 8; }
+// the cooperative pass keeps a few more registers per lane (frontier work)
+constexpr int coop_waves_per_eu(int K) { return K > 16 ? 3 : 5; }
 
 struct TreeArgs {
   const void *nodes;
@@ -55,7 +61,18 @@ struct Kids {
   int32_t lref, rref;
 };
 
-template <int FMT>
+// Child references: r >= 0 is internal node r; r < 0 is a leaf holding
+// primitive ~r.  Whether a node's child slot already holds a leaf's exact
+// box: always for FP32 nodes (the slot is the primitive's box), and for Q16
+// point trees (the slot holds the point's float32 coordinates).  Q16 box
+// trees keep a quantised box in the slot and the exact box in a record
+// addressed by primitive index.
+template <int KIND, int FMT>
+constexpr bool exact_leaf_slots() {
+  return FMT == ABX_NODES_FP32 || KIND == ABX_PRIM_POINTS;
+}
+
+template <int KIND, int FMT>
 __device__ __forceinline__ void load_kids(const TreeArgs &t, int32_t node, Kids &k) {
   if (FMT == ABX_NODES_FP32) {
     const float4 *p = reinterpret_cast<const float4 *>(t.nodes) + 4 * (int64_t)node;
@@ -69,66 +86,65 @@ __device__ __forceinline__ void load_kids(const TreeArgs &t, int32_t node, Kids 
     const uint4 *p = reinterpret_cast<const uint4 *>(t.nodes) + 2 * (int64_t)node;
     const uint4 a = p[0], b = p[1];
     const uint32_t w[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+    k.lref = (int32_t)b.z;
+    k.rref = (int32_t)b.w;
+    const bool pl = KIND == ABX_PRIM_POINTS && k.lref < 0;
+    const bool pr = KIND == ABX_PRIM_POINTS && k.rref < 0;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const uint32_t q = (w[j / 2] >> (16 * (j & 1))) & 0xffffu;
       const int ax = j % 3;
-      k.l[j] = deq(q, t.qs[ax], t.qo[ax]);
+      const float v = deq(q, t.qs[ax], t.qo[ax]);
+      k.l[j] = pl ? __uint_as_float(w[ax]) : v;
     }
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const uint32_t q = (w[3 + j / 2] >> (16 * (j & 1))) & 0xffffu;
       const int ax = j % 3;
-      k.r[j] = deq(q, t.qs[ax], t.qo[ax]);
+      const float v = deq(q, t.qs[ax], t.qo[ax]);
+      k.r[j] = pr ? __uint_as_float(w[3 + ax]) : v;
     }
-    k.lref = (int32_t)b.z;
-    k.rref = (int32_t)b.w;
   }
 }
 
-// exact box of the leaf at sorted position `leaf` (Q16 leaf record) and its
-// primitive's index
-template <int KIND>
-__device__ __forceinline__ int32_t load_leaf_q16(const TreeArgs &t, int32_t leaf, float b[6]) {
-  if (KIND == ABX_PRIM_POINTS) {
-    const float4 v = reinterpret_cast<const float4 *>(t.leaves)[leaf];
-    b[0] = b[3] = v.x;
-    b[1] = b[4] = v.y;
-    b[2] = b[5] = v.z;
-    return __float_as_int(v.w);
-  } else {
-    const float4 *p = reinterpret_cast<const float4 *>(t.leaves) + 2 * (int64_t)leaf;
-    const float4 u = p[0], v = p[1];
-    b[0] = u.x; b[1] = u.y; b[2] = u.z; b[3] = u.w; b[4] = v.x; b[5] = v.y;
-    return __float_as_int(v.z);
-  }
+// exact box of primitive `idx` of a Q16 box tree (its leaf record)
+__device__ __forceinline__ void load_leaf_box(const TreeArgs &t, int32_t idx, float b[6]) {
+  const float4 *p = reinterpret_cast<const float4 *>(t.leaves) + 2 * (int64_t)idx;
+  const float4 u = p[0], v = p[1];
+  b[0] = u.x; b[1] = u.y; b[2] = u.z; b[3] = u.w; b[4] = v.x; b[5] = v.y;
 }
 
-// Per-lane stack: entry e of lane t lives at lds[e * kTravBlock + t] for
-// e < S, else at ovf[e - S] in the lane's private memory.  The LDS part is
-// addressed through an explicit LDS (address space 3) pointer so that the
-// two paths stay separate instructions (the compiler would otherwise merge
-// them into one generic flat access, slower on the common LDS path).
+// Per-lane stack with its top in LDS.  Positions [sp - nl, sp) (at most S
+// entries) live in a circular LDS window, slot (position mod S) of the
+// lane's column (stride B lanes); deeper positions live in the lane's
+// private memory at ovf[position].  A push into a full window first moves
+// the window's bottom entry to private memory; a pop from an empty window
+// reads private memory directly.  A walk that pushes and pops near the top
+// (a depth-first traversal oscillating around some depth) therefore stays in
+// LDS, and private memory is touched only when the depth drifts by more than
+// S.  The LDS part is addressed through an explicit LDS (address space 3)
+// pointer so the two paths stay separate instructions.
 #define ABX_LDS __attribute__((address_space(3)))
 
 template <typename T, int S, int B>
-__device__ __forceinline__ void stack_push(ABX_LDS T *lds, T *ovf, int &sp, T x) {
-  if (sp < S) {
-    lds[sp * B] = x;
-  } else {
-    ovf[sp - S] = x;
-  }
+__device__ __forceinline__ void stack_push(ABX_LDS T *lds, T *ovf, int &sp, int &nl, T x) {
+  static_assert((S & (S - 1)) == 0, "window size is a power of two");
+  const int slot = (sp & (S - 1)) * B;
+  if (nl == S) ovf[sp - S] = lds[slot];
+  else ++nl;
+  lds[slot] = x;
   ++sp;
 }
 
 template <typename T, int S, int B>
-__device__ __forceinline__ T stack_pop(ABX_LDS T *lds, const T *ovf, int &sp) {
+__device__ __forceinline__ T stack_pop(ABX_LDS T *lds, const T *ovf, int &sp, int &nl) {
   --sp;
   T v;
-  if (sp < S) {
-    v = lds[sp * B];
+  if (nl > 0) {
+    --nl;
+    v = lds[(sp & (S - 1)) * B];
   } else {
-    v = ovf[sp - S];
+    v = ovf[sp];
   }
   return v;
 }
@@ -136,87 +152,91 @@ __device__ __forceinline__ T stack_pop(ABX_LDS T *lds, const T *ovf, int &sp) {
 // the nearest traversal's stack holds (node, box distance) pairs
 template <int S, int B>
 __device__ __forceinline__ void stack_push2(ABX_LDS int32_t *ln, ABX_LDS float *ld, int32_t *on,
-                                            float *od, int &sp, int32_t n, float d) {
-  if (sp < S) {
-    ln[sp * B] = n;
-    ld[sp * B] = d;
+                                            float *od, int &sp, int &nl, int32_t n, float d) {
+  static_assert((S & (S - 1)) == 0, "window size is a power of two");
+  const int slot = (sp & (S - 1)) * B;
+  if (nl == S) {
+    on[sp - S] = ln[slot];
+    od[sp - S] = ld[slot];
   } else {
-    on[sp - S] = n;
-    od[sp - S] = d;
+    ++nl;
   }
+  ln[slot] = n;
+  ld[slot] = d;
   ++sp;
 }
 
 template <int S, int B>
 __device__ __forceinline__ void stack_pop2(ABX_LDS int32_t *ln, ABX_LDS float *ld, const int32_t *on,
-                                           const float *od, int &sp, int32_t &n, float &d) {
+                                           const float *od, int &sp, int &nl, int32_t &n, float &d) {
   --sp;
-  if (sp < S) {
-    n = ln[sp * B];
-    d = ld[sp * B];
+  if (nl > 0) {
+    --nl;
+    const int slot = (sp & (S - 1)) * B;
+    n = ln[slot];
+    d = ld[slot];
   } else {
-    n = on[sp - S];
-    d = od[sp - S];
+    n = on[sp];
+    d = od[sp];
   }
 }
 
 enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_STATS = 2 };
 
 // ------------------------------------------------------------------ nearest
-// (d, i) precedes (e, j) in (distance, index) order
-__device__ __forceinline__ bool precedes(float d, int32_t i, float e, int32_t j) {
-  return d < e || (d == e && i < j);
+// A candidate (squared distance d, primitive index i) packed into one
+// signed 64-bit key: the float bits of d (d >= 0, so its bit pattern orders
+// like the value) in the high word, i in the low word.  Key order is then
+// exactly the (distance, index) order, and one 64-bit compare replaces the
+// two-field comparison.  NaN distances pack above +inf and are never taken.
+__device__ __forceinline__ int64_t knn_key(float d, int32_t i) {
+  return (int64_t)(((uint64_t)__float_as_uint(d) << 32) | (uint32_t)i);
 }
-
-// Insert (d, idx) -- known to precede the last entry -- into the ascending
-// register list, dropping the last entry.  Fully unrolled: constant register
-// indices only.
-template <int K>
-__device__ __forceinline__ void knn_insert(float (&bd)[K], int32_t (&bi)[K], float d, int32_t idx) {
-  bool after_prev = true;  // x precedes a[j] (true for j = K-1)
-#pragma unroll
-  for (int j = K - 1; j > 0; --j) {
-    const bool lt_prev = precedes(d, idx, bd[j - 1], bi[j - 1]);
-    const float nd = lt_prev ? bd[j - 1] : (after_prev ? d : bd[j]);
-    const int32_t ni = lt_prev ? bi[j - 1] : (after_prev ? idx : bi[j]);
-    bd[j] = nd;
-    bi[j] = ni;
-    after_prev = lt_prev;
-  }
-  if (after_prev) {
-    bd[0] = d;
-    bi[0] = idx;
-  }
+__device__ __forceinline__ float key_dist(int64_t key) {
+  return __uint_as_float((uint32_t)((uint64_t)key >> 32));
 }
+__device__ __forceinline__ int32_t key_index(int64_t key) { return (int32_t)(uint32_t)key; }
 
-// The k best candidates of one lane, ascending by (squared distance, index).
-// Slots [0, K-k) hold sentinels that precede everything and never move; the
-// k live slots start empty (+inf).
+constexpr int64_t kKeySentinel = -1;  // precedes every candidate
+// an empty slot: (+inf, INT_MAX), preceded by every finite candidate
+constexpr int64_t kKeyEmpty = (int64_t)(((uint64_t)0x7f800000u << 32) | 0x7fffffffu);
+
+// The k best candidates of one lane, ascending keys.  Slots [0, K-k) hold
+// sentinels that precede everything and never move; the k live slots start
+// empty.
 template <int K>
 struct KnnList {
-  float bd[K];
-  int32_t bi[K];
+  int64_t key[K];
   __device__ __forceinline__ void init(int k) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const bool dummy = j < K - k;
-      bd[j] = dummy ? -1.0f : INFINITY;
-      bi[j] = dummy ? -1 : INT_MAX;
+    for (int j = 0; j < K; ++j) key[j] = j < K - k ? kKeySentinel : kKeyEmpty;
+  }
+  __device__ __forceinline__ float kth() const { return key_dist(key[K - 1]); }
+  // Insert x if it precedes the last entry, dropping the last entry.  With
+  // c_j = (x < key[j]) (false up to the insertion point, true after it), slot
+  // j keeps its entry, takes x, or takes its predecessor's entry.  Fully
+  // unrolled: constant register indices only.
+  __device__ __forceinline__ void offer_key(int64_t x) {
+    if (x < key[K - 1]) {
+      bool c_prev = x < key[0];
+      int64_t prev = key[0];
+      if (c_prev) key[0] = x;
+#pragma unroll
+      for (int j = 1; j < K; ++j) {
+        const bool c = x < key[j];
+        const int64_t cur = key[j];
+        key[j] = c ? (c_prev ? prev : x) : cur;
+        prev = cur;
+        c_prev = c;
+      }
     }
   }
-  __device__ __forceinline__ float kth() const { return bd[K - 1]; }
-  __device__ __forceinline__ void offer(float d, int32_t idx) {
-    if (precedes(d, idx, bd[K - 1], bi[K - 1])) knn_insert<K>(bd, bi, d, idx);
-  }
-  // drop the front entry (sentinel or taken), pad the back with +inf
+  __device__ __forceinline__ void offer(float d, int32_t idx) { offer_key(knn_key(d, idx)); }
+  // drop the front entry (sentinel or taken), pad the back with an empty slot
   __device__ __forceinline__ void shift() {
 #pragma unroll
-    for (int j = 0; j + 1 < K; ++j) {
-      bd[j] = bd[j + 1];
-      bi[j] = bi[j + 1];
-    }
-    bd[K - 1] = INFINITY;
-    bi[K - 1] = INT_MAX;
+    for (int j = 0; j + 1 < K; ++j) key[j] = key[j + 1];
+    key[K - 1] = kKeyEmpty;
   }
 };
 
@@ -224,20 +244,20 @@ struct KnnQuery {
   float x, y, z;
 };
 
-// A leaf child whose node-stored box is at squared distance dbox: confirm
-// with the exact leaf box (Q16) and offer it to the list.  Candidates beyond
-// `thr` (an upper bound of the final k-th distance) cannot be in the result.
+// A leaf child (primitive idx) whose node-stored box is at squared distance
+// dbox: confirm with the exact box where the slot is quantised, and offer
+// it to the list.  Candidates beyond `thr` (an upper bound of the final k-th
+// distance) cannot be in the result.
 template <int KIND, int FMT, int K>
-__device__ __forceinline__ void knn_leaf(const TreeArgs &t, const KnnQuery &q, int32_t pos,
+__device__ __forceinline__ void knn_leaf(const TreeArgs &t, const KnnQuery &q, int32_t idx,
                                          float dbox, float thr, KnnList<K> &L, int32_t &reads) {
   if (!(dbox <= thr)) return;
-  ++reads;
-  if (FMT == ABX_NODES_FP32) {
-    // the node box of a leaf child is the primitive's exact box
-    L.offer(dbox, reinterpret_cast<const int32_t *>(t.leaves)[pos]);
+  if (exact_leaf_slots<KIND, FMT>()) {
+    L.offer(dbox, idx);
   } else {
+    ++reads;
     float b[6];
-    const int32_t idx = load_leaf_q16<KIND>(t, pos, b);
+    load_leaf_box(t, idx, b);
     const float d = box_dist2(b[0], b[1], b[2], b[3], b[4], b[5], q.x, q.y, q.z);
     if (d <= thr) L.offer(d, idx);
   }
@@ -247,13 +267,13 @@ __device__ __forceinline__ void knn_leaf(const TreeArgs &t, const KnnQuery &q, i
 // return the nearer qualifying internal child (the farther one is pushed),
 // or -1 when neither qualifies.  `bound` is an external upper bound of the
 // final k-th distance (+inf when there is none).
-template <int KIND, int FMT, int K, int B>
+template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest>
 __device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &q, int32_t node,
                                              float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
                                              ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
-                                             int &sp, int32_t &reads) {
+                                             int &sp, int &nl, int32_t &reads) {
   Kids c;
-  load_kids<FMT>(t, node, c);
+  load_kids<KIND, FMT>(t, node, c);
   const float dl = box_dist2(c.l[0], c.l[1], c.l[2], c.l[3], c.l[4], c.l[5], q.x, q.y, q.z);
   const float dr = box_dist2(c.r[0], c.r[1], c.r[2], c.r[3], c.r[4], c.r[5], q.x, q.y, q.z);
   const bool ll = c.lref < 0, lr = c.rref < 0;
@@ -264,8 +284,8 @@ __device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &
   if (gl && gr) {
     const bool left_first = dl <= dr;
     if (sp < kMaxDepth)
-      stack_push2<kLdsDepthNearest, B>(lds_n, lds_d, ovf_n, ovf_d, sp,
-                                       left_first ? c.rref : c.lref, left_first ? dr : dl);
+      stack_push2<S, B>(lds_n, lds_d, ovf_n, ovf_d, sp, nl, left_first ? c.rref : c.lref,
+                        left_first ? dr : dl);
     return left_first ? c.lref : c.rref;
   }
   if (gl) return c.lref;
@@ -274,13 +294,13 @@ __device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &
 }
 
 // pop deferred nodes until one still qualifies; -1 when the stack runs dry
-template <int B>
+template <int B, int S = kLdsDepthNearest>
 __device__ __forceinline__ int32_t knn_pop(float thr, ABX_LDS int32_t *lds_n, ABX_LDS float *lds_d,
-                                           const int32_t *ovf_n, const float *ovf_d, int &sp) {
+                                           const int32_t *ovf_n, const float *ovf_d, int &sp, int &nl) {
   while (sp > 0) {
     int32_t en;
     float ed;
-    stack_pop2<kLdsDepthNearest, B>(lds_n, lds_d, ovf_n, ovf_d, sp, en, ed);
+    stack_pop2<S, B>(lds_n, lds_d, ovf_n, ovf_d, sp, nl, en, ed);
     if (ed <= thr) return en;
   }
   return -1;
@@ -288,7 +308,7 @@ __device__ __forceinline__ int32_t knn_pop(float thr, ABX_LDS int32_t *lds_n, AB
 
 // Where each query's walk starts and where its row goes.
 struct QInfo {
-  int32_t root;        // internal node to start from, or ~leaf for a one-leaf tree
+  int32_t root;        // internal node to start from, or ~primitive for a one-leaf tree
   int kk;              // row length min(k, n of the query's tree)
   int64_t out;         // first output slot of the row
   int32_t base;        // subtracted from primitive indices (tree-local rows)
@@ -315,8 +335,8 @@ __device__ __forceinline__ void knn_write(const KnnList<K> &L, int k, int32_t ba
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     if (j >= K - k) {
-      oi[j - (K - k)] = L.bi[j] - base;
-      od[j - (K - k)] = sqrtf(L.bd[j]);
+      oi[j - (K - k)] = key_index(L.key[j]) - base;
+      od[j - (K - k)] = sqrtf(key_dist(L.key[j]));
     }
   }
 }
@@ -352,17 +372,17 @@ __device__ __forceinline__ void nearest_lane(const TreeArgs &t, const Map &map,
     const float d = box_dist2(b[0], b[1], b[2], b[3], b[4], b[5], q.x, q.y, q.z);
     knn_leaf<KIND, FMT, K>(t, q, ~info.root, d, INFINITY, L, reads);
   } else {
-    int32_t ovf_n[kMaxDepth - kLdsDepthNearest];
-    float ovf_d[kMaxDepth - kLdsDepthNearest];
-    int sp = 0;
+    int32_t ovf_n[kMaxDepth];
+    float ovf_d[kMaxDepth];
+    int sp = 0, nl = 0;
     int32_t node = info.root;
     const int64_t limit = budget < t.n ? budget : t.n;
     done = false;
     for (int64_t it = 0; it < limit; ++it) {
       if (STATS) ++visited;
       node = knn_visit<KIND, FMT, K, B>(t, q, node, INFINITY, L, lds_n, lds_d, ovf_n, ovf_d, sp,
-                                        reads);
-      if (node < 0) node = knn_pop<B>(L.kth(), lds_n, lds_d, ovf_n, ovf_d, sp);
+                                        nl, reads);
+      if (node < 0) node = knn_pop<B>(L.kth(), lds_n, lds_d, ovf_n, ovf_d, sp, nl);
       if (node < 0) {
         done = true;
         break;
@@ -389,9 +409,10 @@ __device__ __forceinline__ float wave_min(float v) {
   return v;
 }
 
-constexpr int kCoopFront = 256;      // frontier size at which the lanes split up
-constexpr int kCoopFrontCap = 1024;  // > 2 * (kCoopFront - 1)
-constexpr int kCoopBlocksPerCU = 6;
+constexpr int kCoopFront = 256;     // frontier size at which the lanes split up
+constexpr int kCoopFrontCap = 512;  // >= 2 * (kCoopFront - 1): one expansion's output
+constexpr int kCoopWindow = kCoopFrontCap / kWave;  // LDS stack entries per lane
+constexpr int kCoopBlocksPerCU = 4 * coop_waves_per_eu(1);
 
 // Pass 2: one wavefront per heavy query (several lanes per query).  The wave
 // expands the tree breadth-first until the frontier holds kCoopFront nodes,
@@ -403,25 +424,25 @@ constexpr int kCoopBlocksPerCU = 6;
 // so the k best of the 64 lists, taken in (distance, index) order, are the
 // exact answer.  Runs as a persistent grid draining the heavy list.
 template <int KIND, int FMT, int K, class Map>
-__global__ __launch_bounds__(kWave) void k_nearest_coop(TreeArgs t, Map map,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(coop_waves_per_eu(K))))
+void k_nearest_coop(TreeArgs t, Map map,
                                                         const float *__restrict__ pts,
                                                         int32_t *__restrict__ indices,
                                                         float *__restrict__ dist, HeavyList heavy) {
+  // two frontier buffers; during the depth-first phase the one not holding
+  // the final frontier is the lanes' stack window
   __shared__ int32_t s_fn[2][kCoopFrontCap];
   __shared__ float s_fd[2][kCoopFrontCap];
-  __shared__ int32_t s_node[kLdsDepthNearest * kWave];
-  __shared__ float s_dist[kLdsDepthNearest * kWave];
-  __shared__ uint32_t s_h;
   const int lane = threadIdx.x;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const uint32_t total = heavy.count[0];
   resolve_qframe(t);
   int32_t reads = 0;
   while (true) {
-    if (lane == 0) s_h = atomicAdd(heavy.count + 1, 1u);
-    __syncthreads();
-    const uint32_t h = s_h;
-    __syncthreads();
+    __syncthreads();  // the previous query's stack window is free again
+    uint32_t h = 0;
+    if (lane == 0) h = atomicAdd(heavy.count + 1, 1u);
+    h = __shfl(h, 0, kWave);
     if (h >= total) break;
     const int32_t qi = heavy.q[h];
     const QInfo info = map.info(qi, t);
@@ -447,7 +468,7 @@ __global__ __launch_bounds__(kWave) void k_nearest_coop(TreeArgs t, Map map,
         float dl = 0.0f, dr = 0.0f;
         if (e < fsize && s_fd[cur][e] <= fminf(L.kth(), bound)) {
           Kids c;
-          load_kids<FMT>(t, s_fn[cur][e], c);
+          load_kids<KIND, FMT>(t, s_fn[cur][e], c);
           dl = box_dist2(c.l[0], c.l[1], c.l[2], c.l[3], c.l[4], c.l[5], q.x, q.y, q.z);
           dr = box_dist2(c.r[0], c.r[1], c.r[2], c.r[3], c.r[4], c.r[5], q.x, q.y, q.z);
           if (c.lref < 0) knn_leaf<KIND, FMT, K>(t, q, ~c.lref, dl, fminf(L.kth(), bound), L, reads);
@@ -479,15 +500,15 @@ __global__ __launch_bounds__(kWave) void k_nearest_coop(TreeArgs t, Map map,
     }
 
     // depth-first walks of the lane's share of the frontier
-    int32_t ovf_n[kMaxDepth - kLdsDepthNearest];
-    float ovf_d[kMaxDepth - kLdsDepthNearest];
-    ABX_LDS int32_t *lds_n = (ABX_LDS int32_t *)(s_node) + lane;
-    ABX_LDS float *lds_d = (ABX_LDS float *)(s_dist) + lane;
-    int sp = 0;
+    int32_t ovf_n[kMaxDepth];
+    float ovf_d[kMaxDepth];
+    ABX_LDS int32_t *lds_n = (ABX_LDS int32_t *)(s_fn[cur ^ 1]) + lane;
+    ABX_LDS float *lds_d = (ABX_LDS float *)(s_fd[cur ^ 1]) + lane;
+    int sp = 0, nl = 0;
     const int mine = fsize > lane ? (fsize - 1 - lane) / kWave + 1 : 0;
     for (int a = mine - 1; a >= 0; --a)
-      stack_push2<kLdsDepthNearest, kWave>(lds_n, lds_d, ovf_n, ovf_d, sp,
-                                           s_fn[cur][lane + kWave * a], s_fd[cur][lane + kWave * a]);
+      stack_push2<kCoopWindow, kWave>(lds_n, lds_d, ovf_n, ovf_d, sp, nl,
+                                      s_fn[cur][lane + kWave * a], s_fd[cur][lane + kWave * a]);
     __syncthreads();
     bool active = true;
     int32_t node = -1;
@@ -495,12 +516,14 @@ __global__ __launch_bounds__(kWave) void k_nearest_coop(TreeArgs t, Map map,
       bound = wave_min(fminf(bound, L.kth()));
       if (!__any(active)) break;
       if (active) {
-        if (node < 0) node = knn_pop<kWave>(fminf(L.kth(), bound), lds_n, lds_d, ovf_n, ovf_d, sp);
+        if (node < 0)
+          node = knn_pop<kWave, kCoopWindow>(fminf(L.kth(), bound), lds_n, lds_d, ovf_n, ovf_d,
+                                             sp, nl);
         if (node < 0) {
           active = false;
         } else {
-          node = knn_visit<KIND, FMT, K, kWave>(t, q, node, bound, L, lds_n, lds_d, ovf_n, ovf_d,
-                                                sp, reads);
+          node = knn_visit<KIND, FMT, K, kWave, kCoopWindow>(t, q, node, bound, L, lds_n, lds_d,
+                                                             ovf_n, ovf_d, sp, nl, reads);
         }
       }
     }
@@ -508,29 +531,22 @@ __global__ __launch_bounds__(kWave) void k_nearest_coop(TreeArgs t, Map map,
     // merge: k rounds of a wave-wide (distance, index) minimum over the
     // lanes' list fronts
     for (int s = 0; s < K - k; ++s) L.shift();
-    float out_d = 0.0f;
-    int32_t out_i = 0;
+    int64_t out = 0;
     for (int j = 0; j < k; ++j) {
-      float d = L.bd[0];
-      int32_t i = L.bi[0];
+      int64_t m = L.key[0];
 #pragma unroll
       for (int o = kWave / 2; o > 0; o >>= 1) {
-        const float d2 = __shfl_xor(d, o, kWave);
-        const int32_t i2 = __shfl_xor(i, o, kWave);
-        if (precedes(d2, i2, d, i)) {
-          d = d2;
-          i = i2;
-        }
+        const int64_t m2 = __shfl_xor(m, o, kWave);
+        m = m2 < m ? m2 : m;
       }
-      if (L.bi[0] == i && L.bd[0] == d) L.shift();
-      if (lane == j) {
-        out_d = d;
-        out_i = i;
-      }
+      // keys are unique (one entry per primitive), so exactly one lane
+      // holds the minimum
+      if (L.key[0] == m) L.shift();
+      if (lane == j) out = m;
     }
     if (lane < k) {
-      indices[info.out + lane] = out_i - info.base;
-      dist[info.out + lane] = sqrtf(out_d);
+      indices[info.out + lane] = key_index(out) - info.base;
+      dist[info.out + lane] = sqrtf(key_dist(out));
     }
   }
   (void)reads;

@@ -95,8 +95,10 @@ def check_nearest(orc, prims, kind, queries, k, gpu_idx, gpu_dist, rows=None):
 
 # ---------------------------------------------------------------- trees
 def decode_tree(bvh):
-    """Child kinds/indices, permutation, node boxes and (for Q16) exact leaf
-    boxes of a built tree, read back from device memory."""
+    """Child kinds/indices (leaves by sorted position, as the hierarchy
+    numbers them), permutation, node boxes and (for Q16) exact leaf boxes
+    in sorted order, read back from device memory.  Leaf references name
+    the primitive (~index); they are mapped back through the permutation."""
     lay = bvh.layout
     n = bvh.n
     ni = max(n - 1, 0)
@@ -115,16 +117,32 @@ def decode_tree(bvh):
         out["q_l"] = u[:, 0:6].astype(np.uint32)
         out["q_r"] = u[:, 6:12].astype(np.uint32)
         if bvh.kind == 0:
-            lf = leaves.view(np.float32).reshape(n, 4)
-            out["perm"] = leaves.view(np.int32).reshape(n, 4)[:, 3].astype(np.int64)
-            out["leaf_boxes"] = np.concatenate([lf[:, :3], lf[:, :3]], axis=1)
+            out["perm"] = leaves.view(np.int32).astype(np.int64)
         else:
-            lf = leaves.view(np.float32).reshape(n, 8)
-            out["perm"] = leaves.view(np.int32).reshape(n, 8)[:, 6].astype(np.int64)
-            out["leaf_boxes"] = lf[:, :6].copy()
+            rec = leaves.view(np.float32).reshape(n, 8)
+            pos = leaves.view(np.int32).reshape(n, 8)[:, 6].astype(np.int64)
+            perm = np.full(n, -1, np.int64)
+            perm[pos] = np.arange(n)
+            out["perm"] = perm
+            out["leaf_boxes"] = rec[perm, :6].copy()
+    perm = out["perm"]
+    inv = np.full(n, -1, np.int64)
+    ok = (perm >= 0) & (perm < n)
+    inv[perm[ok]] = np.nonzero(ok)[0]
     refs = refs.astype(np.int64)
     out["child_kind"] = (refs >= 0).astype(np.int8)
-    out["child_index"] = np.where(refs >= 0, refs, ~refs)
+    out["child_index"] = np.where(refs >= 0, refs, inv[np.clip(~refs, 0, max(n - 1, 0))])
+    if lay.node_format == 1 and bvh.kind == 0:
+        # a point leaf's slot holds the float32 point
+        f = nodes.view(np.float32).reshape(ni, 8)
+        lb = np.full((n, 6), np.nan, np.float32)
+        if n == 1:
+            lb[0] = np.array(bvh.scene, np.float32)
+        for s in range(2):
+            m = refs[:, s] < 0
+            xyz = f[m, 3 * s:3 * s + 3]
+            lb[out["child_index"][m, s]] = np.concatenate([xyz, xyz], axis=1)
+        out["leaf_boxes"] = lb
     return out
 
 
