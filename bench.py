@@ -32,7 +32,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C4", "C5", "COPY"])
+    ap.add_argument("--workload", default="C3",
+                    choices=["C1", "C2", "C3", "C4", "C5", "COPY", "PAPER"])
     ap.add_argument("--nodes", default="q16", choices=["fp32", "q16"])
     ap.add_argument("--morton-bits", type=int, default=21)
     ap.add_argument("--k", type=int, default=10)
@@ -44,6 +45,8 @@ def parse():
                     help="requests per load level of the serving block (0: skip it)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--trees", type=int, default=256, help="forest size (C4)")
+    ap.add_argument("--paper-sizes", default="1e4,1e5,1e6,1e7",
+                    help="m = n sweep of the paper's filled and hollow cases (PAPER)")
     return ap.parse_args()
 
 
@@ -71,6 +74,9 @@ def main():
         return
     if args.workload == "C5":
         print(json.dumps(bench_serving(args, standalone=True)), flush=True)
+        return
+    if args.workload == "PAPER":
+        print(json.dumps(bench_paper(args)), flush=True)
         return
     if args.workload == "COPY":
         # plain 1 GiB device copy: the reference for scaling HBM counters
@@ -231,6 +237,67 @@ def forest_inputs(n_trees, seed=401):
         qs.append(q)
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     return np.concatenate(pts), off, np.concatenate(qs), off.copy()
+
+
+def bench_paper(args):
+    """The paper's two experimental cases (section 3, data sets) over m = n:
+    filled (filled-sphere queries in a filled-cube cloud) and hollow
+    (hollow-sphere queries in a hollow-cube cloud), kNN k = 10 and radius
+    search with r set for 10 neighbours on average in the filled cube, with
+    the query ordering on and off.  Reports medians of per-phase HIP-event
+    times and the radius neighbour-count statistics the paper quotes."""
+    import torch
+    from paper_1908_11807_amd import abx, datagen
+
+    dev = torch.device("cuda:0")
+    sizes = [int(float(x)) for x in args.paper_sizes.split(",") if x]
+    reps = max(args.steps, 1)
+    rows = []
+
+    def timed(fn):
+        fn()                                   # warm-up
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            out = fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts)), out
+
+    for case in ("filled", "hollow"):
+        for p in sizes:
+            if case == "filled":
+                prims = datagen.paper_filled_cube(p, 601)
+                queries = datagen.paper_filled_sphere(p, 602)
+            else:
+                prims = datagen.paper_hollow_cube(p, 603)
+                queries = datagen.paper_hollow_sphere(p, 604)
+            # 10 neighbours on average in the filled cube [-a, a]^3 (volume 8p)
+            r = datagen.radius_for_density(p, 10, volume=8.0 * p)
+            pts = torch.from_numpy(prims).to(dev)
+            qs = torch.from_numpy(queries).to(dev)
+            build_ms, t = timed(lambda: abx.bvh_build(pts, node_format=args.nodes))
+            row = dict(case=case, n=p, m=p, radius=r, build_ms=round(build_ms, 4),
+                       build_mprims_s=round(p / build_ms / 1e3, 1))
+            for srt in (True, False):
+                tag = "sorted" if srt else "unsorted"
+                knn_ms, _ = timed(lambda: abx.query_nearest(t, qs, 10, sort_queries=srt))
+                rad_ms, (off, _) = timed(lambda: abx.query_spatial(t, qs, radius=r, sort_queries=srt))
+                row[f"knn_ms_{tag}"] = round(knn_ms, 4)
+                row[f"knn_qps_{tag}"] = round(p / knn_ms * 1e3, 1)
+                row[f"radius_ms_{tag}"] = round(rad_ms, 4)
+                row[f"radius_qps_{tag}"] = round(p / rad_ms * 1e3, 1)
+            cnt = torch.diff(off).cpu().numpy()
+            row["neighbours"] = dict(mean=round(float(cnt.mean()), 3), min=int(cnt.min()),
+                                     max=int(cnt.max()))
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            del t, pts, qs
+    return {"metric": "paper cases: build Mprims/s, kNN and radius queries/s over m = n",
+            "workload": "PAPER", "nodes": args.nodes, "k": 10, "reps": reps,
+            "data": "synthetic (the paper's four generators)", "rows": rows}
 
 
 def bench_forest(args):

@@ -81,10 +81,23 @@ typedef struct {
   int64_t n;
 } abx_primitives;
 
+/* Construction of the hierarchy (section 2.1).
+ *   KARRAS       : one thread per internal node finds its range and split by
+ *                  binary searches (Karras 2012), then an atomic bottom-up
+ *                  refit; internal node 0 is the root.
+ *   AGGLOMERATIVE: hierarchy and refit in one bottom-up pass, each node
+ *                  merging with the neighbour of longer common prefix
+ *                  (Apetrei 2014, which the paper plans to adopt); internal
+ *                  node p is the split between sorted positions p and p+1 and
+ *                  the root is reported in the layout.  Same tree, other
+ *                  numbering; queries give identical results. */
+typedef enum { ABX_HIERARCHY_KARRAS = 0, ABX_HIERARCHY_AGGLOMERATIVE = 1 } abx_hierarchy;
+
 typedef struct {
   abx_node_format node_format;
   int32_t morton_bits; /* bits per axis of the Morton code: 10 (30-bit codes)
                           or 21 (63-bit codes, the default when 0) */
+  int32_t hierarchy;   /* abx_hierarchy (0: Karras) */
 } abx_build_options;
 
 /* Spatial predicates (section 2.2, spatial traversal). */
@@ -112,6 +125,8 @@ typedef struct {
   int32_t node_format;    /* abx_node_format                                */
   int32_t morton_bits;
   int32_t height;         /* longest root-to-leaf edge count (0 if n <= 1)  */
+  int32_t hierarchy;      /* abx_hierarchy the tree was built with          */
+  int32_t root;           /* internal node at the root (n >= 2)             */
   float scene[6];         /* scene box lo xyz, hi xyz (section 2.1)         */
   size_t nodes_offset;    /* byte offset of internal node 0 in tree memory */
   size_t node_bytes;      /* 64 (FP32) or 32 (Q16)                          */
@@ -166,6 +181,31 @@ abx_status abx_query_spatial(const abx_bvh *bvh, const abx_predicates *preds, vo
 abx_status abx_query_spatial_fill(const abx_bvh *bvh, const abx_predicates *preds, void *scratch,
                                   size_t scratch_bytes, const int32_t *offsets, int32_t *indices,
                                   int64_t capacity, abx_stream_t stream);
+
+/* -- spatial queries, one pass (section 2.2, the 1P scheme) ---------------
+ * abx_query_spatial_1p_sizes: scratch bytes for m predicates with a per-query
+ *   estimate buffer_size (1 .. 65536) of the hits: the 2P scratch plus
+ *   m * buffer_size int32 slots.
+ * abx_query_spatial_1p: orders the queries (optional), then ONE traversal
+ *   counts every query's hits and stores the first buffer_size of them in
+ *   scratch; the counts are scanned into offsets[0..m] (caller's order,
+ *   offsets[m] = total).  If no query found more than buffer_size hits, the
+ *   stored rows are compacted into indices: one traversal in all.  Otherwise
+ *   the fill traversal of the 2P scheme writes indices (the count is
+ *   already known): two traversals, as 2P.  Nothing blocks the host and
+ *   nothing is read back, so the call can be captured in a graph.
+ *   info (device int32[2]) receives, once the stream has passed the call:
+ *   info[0] = ABX_OK, or ABX_ERR_CAPACITY when total > capacity (offsets
+ *   valid, indices untouched: call abx_query_spatial_fill with the same
+ *   scratch and a large enough buffer), or ABX_ERR_OVERFLOW when total
+ *   reaches 2^31; info[1] = traversals made (0 for an empty tree or batch).
+ *   Within a row the order is the traversal's, as in 2P. */
+abx_status abx_query_spatial_1p_sizes(const abx_bvh *bvh, const abx_predicates *preds,
+                                      int32_t buffer_size, size_t *scratch_bytes /*host*/);
+abx_status abx_query_spatial_1p(const abx_bvh *bvh, const abx_predicates *preds, int32_t buffer_size,
+                                void *scratch, size_t scratch_bytes, int32_t *offsets /*[m+1]*/,
+                                int32_t *indices, int64_t capacity, int32_t *info /*device [2]*/,
+                                abx_stream_t stream);
 
 /* -- nearest queries (section 2.2 nearest traversal) ----------------------
  * abx_query_nearest: for each of the m query points, the min(k, n) nearest

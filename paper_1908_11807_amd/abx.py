@@ -11,6 +11,7 @@ Entry points (same names as the C-ABI, ``abx_`` prefix dropped):
 * ``bvh_build(prims, kind=None, node_format="fp32", morton_bits=21) -> BVH``
 * ``query_spatial(bvh, data, radius=..., radii=None, predicate="within",
   sort_queries=True, capacity=None) -> (offsets, indices)``
+* ``query_spatial_1p(bvh, data, buffer_size, ...) -> (offsets, indices, traversals)``
 * ``query_nearest(bvh, points, k, sort_queries=True) -> (offsets, indices, distances)``
 * ``query_spatial_stats`` / ``query_nearest_stats`` -> int32 [m, 2]
 * ``morton_codes``, ``radix_sort_pairs`` (building blocks)
@@ -33,6 +34,7 @@ NODES_FP32, NODES_Q16 = 0, 1
 PRED_WITHIN, PRED_INTERSECTS_BOX = 0, 1
 
 _FORMATS = {"fp32": NODES_FP32, "q16": NODES_Q16, NODES_FP32: NODES_FP32, NODES_Q16: NODES_Q16}
+_HIERARCHIES = {"karras": 0, "agglomerative": 1}
 _PREDS = {"within": PRED_WITHIN, "intersects": PRED_INTERSECTS_BOX,
           PRED_WITHIN: PRED_WITHIN, PRED_INTERSECTS_BOX: PRED_INTERSECTS_BOX}
 
@@ -52,7 +54,7 @@ class Primitives(C.Structure):
 
 
 class BuildOptions(C.Structure):
-    _fields_ = [("node_format", C.c_int), ("morton_bits", C.c_int32)]
+    _fields_ = [("node_format", C.c_int), ("morton_bits", C.c_int32), ("hierarchy", C.c_int32)]
 
 
 class Predicates(C.Structure):
@@ -102,7 +104,8 @@ REQ_RADIUS, REQ_NEAREST = 0, 1
 
 class Layout(C.Structure):
     _fields_ = [("n", C.c_int64), ("kind", C.c_int32), ("node_format", C.c_int32),
-                ("morton_bits", C.c_int32), ("height", C.c_int32), ("scene", C.c_float * 6),
+                ("morton_bits", C.c_int32), ("height", C.c_int32), ("hierarchy", C.c_int32),
+                ("root", C.c_int32), ("scene", C.c_float * 6),
                 ("nodes_offset", C.c_size_t), ("node_bytes", C.c_size_t),
                 ("leaves_offset", C.c_size_t), ("leaf_bytes", C.c_size_t),
                 ("q16_origin", C.c_float * 3), ("q16_scale", C.c_float * 3)]
@@ -128,6 +131,8 @@ def _lib():
             "abx_query_spatial_sizes": [vp, P(Predicates), P(sz)],
             "abx_query_spatial": [vp, P(Predicates), vp, sz, vp, vp, i64, P(i64), vp],
             "abx_query_spatial_fill": [vp, P(Predicates), vp, sz, vp, vp, i64, vp],
+            "abx_query_spatial_1p_sizes": [vp, P(Predicates), i32, P(sz)],
+            "abx_query_spatial_1p": [vp, P(Predicates), i32, vp, sz, vp, vp, i64, vp, vp],
             "abx_query_nearest_sizes": [vp, i64, i32, P(sz)],
             "abx_query_nearest": [vp, vp, i64, i32, i32, vp, sz, vp, vp, vp, vp],
             "abx_query_spatial_stats": [vp, P(Predicates), vp, sz, vp, vp],
@@ -257,15 +262,18 @@ class BVH:
             _LIB.abx_bvh_destroy(h)
 
 
-def bvh_build(prims, kind=None, node_format="fp32", morton_bits=21):
-    """Build the LBVH of ``prims`` (float32 CUDA tensor, [n,3] points or [n,6] boxes)."""
+def bvh_build(prims, kind=None, node_format="fp32", morton_bits=21, hierarchy="karras"):
+    """Build the LBVH of ``prims`` (float32 CUDA tensor, [n,3] points or [n,6] boxes).
+
+    ``hierarchy``: "karras" (per-node range search, then refit) or
+    "agglomerative" (hierarchy and refit in one bottom-up pass)."""
     L = _lib()
     if kind is None:
         kind = PRIM_BOXES if (prims.dim() == 2 and prims.shape[-1] == 6) else PRIM_POINTS
     width = 3 if kind == PRIM_POINTS else 6
     p = _dev_f32(prims, width, "primitives")
     pr = Primitives(kind, p.data_ptr() if p.numel() else None, p.shape[0])
-    opt = BuildOptions(_FORMATS[node_format], int(morton_bits))
+    opt = BuildOptions(_FORMATS[node_format], int(morton_bits), _HIERARCHIES[hierarchy])
     tb, sb = C.c_size_t(), C.c_size_t()
     _check(L.abx_bvh_build_sizes(C.byref(pr), C.byref(opt), C.byref(tb), C.byref(sb)),
            "abx_bvh_build_sizes")
@@ -319,6 +327,43 @@ def query_spatial(bvh, data, radius=None, radii=None, predicate="within", sort_q
                                       _ptr(offsets), _ptr(indices), total.value, _stream())
     _check(st, "abx_query_spatial")
     return offsets, indices[: total.value]
+
+
+def query_spatial_1p(bvh, data, buffer_size, radius=None, radii=None, predicate="within",
+                     sort_queries=True, capacity=None):
+    """One-pass spatial query -> (offsets, indices, traversals made).
+
+    ``buffer_size`` is the per-query estimate of the hits (the paper's
+    buffer_size): when no query exceeds it, one traversal answers the batch
+    and the stored rows are compacted; otherwise the fill traversal of the
+    two-pass scheme runs.  ``capacity`` (default m * buffer_size) sizes the
+    index buffer; a larger total is allocated after reading it back.
+    """
+    L = _lib()
+    pr, d, rr = _preds(data, predicate, radius, radii, sort_queries)
+    m = d.shape[0]
+    sb = C.c_size_t()
+    _check(L.abx_query_spatial_1p_sizes(bvh.handle, C.byref(pr), int(buffer_size), C.byref(sb)),
+           "abx_query_spatial_1p_sizes")
+    scratch = _bytes(sb.value, d.device)
+    offsets = torch.empty(m + 1, dtype=torch.int32, device=d.device)
+    cap = int(capacity if capacity is not None else m * int(buffer_size))
+    indices = torch.empty(max(cap, 1), dtype=torch.int32, device=d.device)
+    info = torch.zeros(2, dtype=torch.int32, device=d.device)
+    _check(L.abx_query_spatial_1p(bvh.handle, C.byref(pr), int(buffer_size), _ptr(scratch), sb.value,
+                                  _ptr(offsets), _ptr(indices) if cap > 0 else C.c_void_p(0), cap,
+                                  _ptr(info), _stream()), "abx_query_spatial_1p")
+    st, passes = (int(v) for v in info.cpu().tolist())
+    total = int(offsets[-1].item())
+    if st == ERR_CAPACITY:
+        indices = torch.empty(max(total, 1), dtype=torch.int32, device=d.device)
+        _check(L.abx_query_spatial_fill(bvh.handle, C.byref(pr), _ptr(scratch), sb.value,
+                                        _ptr(offsets), _ptr(indices), total, _stream()),
+               "abx_query_spatial_fill")
+        passes = 2
+    else:
+        _check(st, "abx_query_spatial_1p")
+    return offsets, indices[:total], passes
 
 
 def query_nearest(bvh, points, k, sort_queries=True):

@@ -1,5 +1,6 @@
 // C-ABI of libabx: argument validation, buffer layout, the launch sequence of
 // each entry point and the diagnostics.  No device memory is allocated here.
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <map>
@@ -26,6 +27,10 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
                         TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
                         uint32_t *frontier_count, hipStream_t s);
 size_t refit_frontier_cap(int64_t n);
+abx_status launch_agglo(bool wide, int kind, bool q16, const void *keys, const float *prims,
+                        const int32_t *perm, int64_t n, NodeF32 *nodes, int32_t *range_lo,
+                        int32_t *range_hi, uint32_t *flags, TreeHeader *hdr, void *q16_leaves,
+                        int32_t *frontier, uint32_t *frontier_count, hipStream_t s);
 abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, const TreeHeader *hdr, NodeQ16 *dst,
                            hipStream_t s);
 // traverse.hip
@@ -33,7 +38,11 @@ abx_status launch_query_codes(const abx_bvh *b, const float *q, int64_t m, int w
                               uint32_t *codes, hipStream_t s);
 abx_status launch_spatial(const abx_bvh *b, int pred, const float *data, int64_t m,
                           const float *radii, float radius, const int32_t *order, int mode,
-                          int32_t *counts, const int32_t *offsets, int32_t *indices, hipStream_t s);
+                          int32_t *counts, const int32_t *offsets, int32_t *indices, hipStream_t s,
+                          const OnePass *op = nullptr);
+abx_status launch_spatial_compact(const OnePass &op, int64_t m, const int32_t *order,
+                                  const int32_t *counts, const int32_t *offsets, int32_t *indices,
+                                  int32_t *info, int64_t max_count, hipStream_t s);
 abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order,
                           int k, int32_t *idx, float *dist, int32_t *stats, int32_t *heavy_q,
                           float *heavy_bound, uint32_t *counters, int64_t budget, hipStream_t s);
@@ -95,6 +104,8 @@ abx_status check_build_args(const abx_primitives *p, const abx_build_options *o)
     return ABX_ERR_INVALID_ARG;
   const int bits = resolve_bits(o);
   if (bits != 10 && bits != 21) return ABX_ERR_INVALID_ARG;
+  if (o && o->hierarchy != ABX_HIERARCHY_KARRAS && o->hierarchy != ABX_HIERARCHY_AGGLOMERATIVE)
+    return ABX_ERR_INVALID_ARG;
   return ABX_OK;
 }
 
@@ -356,6 +367,7 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
   TreeHeader *hdr = reinterpret_cast<TreeHeader *>(tree);
   const int64_t n = L.n;
   const int kind = prims->kind;
+  const bool agglo = opts && opts->hierarchy == ABX_HIERARCHY_AGGLOMERATIVE;
 
   const int blocks = scene_blocks(n);
   ABX_TRY(launch_scene(kind, prims->data, n, reinterpret_cast<float *>(sc + L.partial), blocks, hdr, s));
@@ -371,12 +383,19 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
     ABX_TRY(launch_morton(kind, prims->data, n, hdr->scene, L.bits, sc + L.codes, L.wide, s));
     ABX_TRY(radix_sort(sc + L.codes, nullptr, n, 3 * L.bits, sc + L.sorted, perm, sc + L.sort,
                        radix_sort_scratch_bytes(n, 3 * L.bits), s));
-    ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, fnodes, parent_leaf, parent_int, other_end,
-                          flags, s));
     uint32_t *fcount = reinterpret_cast<uint32_t *>(sc + L.frontier);
     int32_t *frontier = reinterpret_cast<int32_t *>(sc + L.frontier + 256);
-    ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, parent_leaf, parent_int, other_end,
-                         fnodes, flags, hdr, tree + L.leaves_off, frontier, fcount, s));
+    if (agglo) {
+      // range ends of the agglomerative climb reuse the parent arrays
+      ABX_TRY(launch_agglo(L.wide, kind, L.q16, sc + L.sorted, prims->data, perm, n, fnodes,
+                           parent_leaf, parent_int, flags, hdr, tree + L.leaves_off, frontier,
+                           fcount, s));
+    } else {
+      ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, fnodes, parent_leaf, parent_int, other_end,
+                            flags, s));
+      ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, parent_leaf, parent_int, other_end,
+                           fnodes, flags, hdr, tree + L.leaves_off, frontier, fcount, s));
+    }
     if (L.q16)
       ABX_TRY(launch_quantise(kind, fnodes, L.ni, hdr, reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
   }
@@ -397,6 +416,8 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
   b->format = L.q16 ? ABX_NODES_Q16 : ABX_NODES_FP32;
   b->morton_bits = L.bits;
   b->height = h.height;
+  b->hierarchy = agglo ? ABX_HIERARCHY_AGGLOMERATIVE : ABX_HIERARCHY_KARRAS;
+  b->root = h.root;
   std::memcpy(b->scene, h.scene, sizeof(b->scene));
   std::memcpy(b->q_origin, h.q_origin, sizeof(b->q_origin));
   std::memcpy(b->q_scale, h.q_scale, sizeof(b->q_scale));
@@ -422,6 +443,8 @@ abx_status abx_bvh_get_layout(const abx_bvh *b, abx_bvh_layout *o) {
   o->node_format = b->format;
   o->morton_bits = b->morton_bits;
   o->height = b->height;
+  o->hierarchy = b->hierarchy;
+  o->root = b->root;
   std::memcpy(o->scene, b->scene, sizeof(o->scene));
   o->nodes_offset = b->nodes_off;
   o->node_bytes = b->node_bytes;
@@ -503,6 +526,60 @@ abx_status abx_query_spatial_fill(const abx_bvh *bvh, const abx_predicates *pred
   const int32_t *order = preds->sort_queries ? reinterpret_cast<const int32_t *>(sc + L.order) : nullptr;
   return launch_spatial(bvh, preds->kind, preds->data, m, preds->radii, preds->radius, order,
                         1 /*fill*/, nullptr, offsets, indices, s);
+}
+
+// ---------------------------------------------------------------- spatial, one pass
+constexpr int32_t kMaxBufferSize = 1 << 16;
+
+// scratch beyond the query layout: 256 B of flags, then the stored rows
+static size_t one_pass_bytes(int64_t m, int32_t bufsize) {
+  return 256 + align_up((size_t)m * (size_t)bufsize * 4, 256);
+}
+
+abx_status abx_query_spatial_1p_sizes(const abx_bvh *bvh, const abx_predicates *preds,
+                                      int32_t buffer_size, size_t *scratch_bytes) {
+  ABX_TRY(check_bvh(bvh));
+  ABX_TRY(check_preds(preds));
+  if (!scratch_bytes || buffer_size < 1 || buffer_size > kMaxBufferSize) return ABX_ERR_INVALID_ARG;
+  *scratch_bytes = query_layout(preds->m).bytes + one_pass_bytes(preds->m, buffer_size);
+  return ABX_OK;
+}
+
+abx_status abx_query_spatial_1p(const abx_bvh *bvh, const abx_predicates *preds, int32_t buffer_size,
+                                void *scratch, size_t scratch_bytes, int32_t *offsets,
+                                int32_t *indices, int64_t capacity, int32_t *info,
+                                abx_stream_t stream) {
+  QueryLayout L;
+  ABX_TRY(spatial_prologue(bvh, preds, scratch, scratch_bytes, &L));
+  if (buffer_size < 1 || buffer_size > kMaxBufferSize) return ABX_ERR_INVALID_ARG;
+  const int64_t m = preds->m;
+  if (scratch_bytes < L.bytes + one_pass_bytes(m, buffer_size)) return ABX_ERR_INVALID_ARG;
+  if (!offsets || !info || capacity < 0 || (capacity > 0 && !indices)) return ABX_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *sc = static_cast<char *>(scratch);
+  int64_t *d_total = reinterpret_cast<int64_t *>(sc + L.total);
+  uint32_t *flag = reinterpret_cast<uint32_t *>(sc + L.bytes);
+  int32_t *buf = reinterpret_cast<int32_t *>(sc + L.bytes + 256);
+  const OnePass op{buf, buffer_size, flag, d_total, std::min<int64_t>(capacity, kMaxCount - 1)};
+  ABX_TRY(fill_u32(flag, 0, 4, s));
+  if (bvh->n == 0 || m == 0) {
+    ABX_TRY(fill_u32(offsets, 0, (size_t)m + 1, s));
+    ABX_TRY(fill_u32(d_total, 0, 2, s));
+    return fill_u32(info, 0, 2, s);  // ABX_OK, no traversal
+  }
+  const int width = preds->kind == ABX_PRED_WITHIN ? 3 : 6;
+  const int32_t *order = nullptr;
+  if (preds->sort_queries) ABX_TRY(order_queries(bvh, preds->data, m, width, sc, L, &order, s));
+  int32_t *counts = reinterpret_cast<int32_t *>(sc + L.counts);
+  // one traversal counts every hit and stores the first buffer_size of each row
+  ABX_TRY(launch_spatial(bvh, preds->kind, preds->data, m, preds->radii, preds->radius, order,
+                         3 /*store*/, counts, nullptr, nullptr, s, &op));
+  ABX_TRY(exclusive_scan(counts, m, offsets, d_total, sc + L.scan, scan_scratch_bytes(m), s));
+  // after an overflow: the fill traversal of the two-pass scheme (the
+  // kernel returns at once otherwise); without one: compaction
+  ABX_TRY(launch_spatial(bvh, preds->kind, preds->data, m, preds->radii, preds->radius, order,
+                         1 /*fill*/, nullptr, offsets, indices, s, &op));
+  return launch_spatial_compact(op, m, order, counts, offsets, indices, info, kMaxCount, s);
 }
 
 abx_status abx_query_spatial_stats(const abx_bvh *bvh, const abx_predicates *preds, void *scratch,

@@ -32,7 +32,8 @@ struct TreeHeader {
   float q_scale[3];
   int32_t bad;        // 1 if a coordinate was NaN or infinite
   int32_t height;     // longest root-to-leaf path (edges)
-  int32_t pad[47];
+  int32_t root;       // internal node at the root (0 for the Karras numbering)
+  int32_t pad[46];
 };
 static_assert(sizeof(TreeHeader) == 256, "header is 256 B");
 
@@ -154,9 +155,20 @@ abx_status exclusive_scan(const int32_t *counts, int64_t m, int32_t *offsets, in
 }  // namespace abx
 
 // Opaque handle definition (host memory).
+// State of a one-pass (1P) spatial query in the caller's scratch: the stored
+// rows, the overflow flag and the scanned total, and the caller's capacity.
+struct OnePass {
+  int32_t *buf;          // [m * bufsize]
+  int32_t bufsize;
+  uint32_t *flag;        // [0] overflow seen
+  const int64_t *total;
+  int64_t capacity;
+};
+
 struct abx_bvh {
   int64_t n;
   int32_t kind, format, morton_bits, height;
+  int32_t hierarchy, root;  // construction used; internal node at the root
   float scene[6];
   float q_origin[3], q_scale[3];
   char *tree;  // device base

@@ -103,6 +103,7 @@ __global__ void k_header_init(TreeHeader *hdr) {
   if (threadIdx.x == 0) {
     hdr->bad = 0;
     hdr->height = 0;
+    hdr->root = 0;  // Karras numbering; the agglomerative build overwrites it
   }
 }
 
@@ -361,6 +362,149 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_top(const int32_t *__re
   }
 }
 
+// ------------------------------------------------- agglomerative build
+// Hierarchy and refit in one bottom-up pass (Apetrei 2014, the single-pass
+// construction the paper intends to adopt, section 2.1).  Internal node p is
+// the split between sorted positions p and p+1.  A node covering [l, r]
+// joins the neighbour it shares the longer augmented-code prefix with: its
+// parent is split r (it is the left child) when delta(r, r+1) >
+// delta(l-1, l), else split l-1 (right child); the two can never tie.  The
+// tree is the same binary radix tree as the Karras build, numbered by split.
+//
+// Phase 1 (one workgroup per chunk of kRefitChunk leaves): a leaf's thread
+// climbs while the parent's split lies strictly inside the chunk (both of
+// its children then hold a leaf of the chunk, so any arrival in this phase
+// comes from this workgroup): it writes its box, reference, height and range
+// end into the parent, then counts its arrival in LDS (workgroup scope); the
+// second arrival reads the sibling back and climbs on.  An arrival at a
+// split between two chunks is appended to the frontier instead.  At the
+// end, each split of the chunk hands its count to the top pass (1 if exactly
+// one child arrived, else 0).
+// Phase 2 (one workgroup, after the kernel boundary): climbs from every
+// frontier entry with global counters, again at workgroup scope.
+template <typename K, int KIND, bool kQ16>
+__global__ __launch_bounds__(kRefitThreads) void k_agglo_local(
+    const K *__restrict__ keys, const float *__restrict__ prims, const int32_t *__restrict__ perm,
+    int64_t n, NodeF32 *nodes, int32_t *range_lo, int32_t *range_hi, uint32_t *__restrict__ flags,
+    TreeHeader *hdr, void *q16_leaves, int32_t *__restrict__ frontier,
+    uint32_t *__restrict__ frontier_count, uint32_t frontier_cap) {
+  __shared__ uint32_t s_cnt[kRefitChunk];
+  for (int i = threadIdx.x; i < kRefitChunk; i += kRefitThreads) s_cnt[i] = 0;
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kRefitChunk;
+  const int64_t c1 = c0 + kRefitChunk < n ? c0 + kRefitChunk : n;
+  for (int rr = 0; rr < kRefitPerThread; ++rr) {
+    const int64_t p0 = c0 + (int64_t)rr * kRefitThreads + threadIdx.x;
+    if (p0 >= c1) break;
+    const int32_t orig = perm[p0];
+    float b[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      b[a] = KIND == ABX_PRIM_POINTS ? prims[3 * (int64_t)orig + a] : prims[6 * (int64_t)orig + a];
+      b[3 + a] = KIND == ABX_PRIM_POINTS ? b[a] : prims[6 * (int64_t)orig + 3 + a];
+    }
+    if (kQ16 && KIND == ABX_PRIM_BOXES) {
+      float4 *o = reinterpret_cast<float4 *>(q16_leaves) + 2 * (int64_t)orig;
+      o[0] = make_float4(b[0], b[1], b[2], b[3]);
+      o[1] = make_float4(b[4], b[5], __int_as_float((int32_t)p0), 0.0f);
+    }
+    if (n == 1) break;
+    int64_t l = p0, r = p0;
+    int32_t ref = ~orig;
+    int h = 0;
+    for (int step = 0; step < kRefitMaxSteps; ++step) {
+      const bool left = l == 0 || (r != n - 1 && delta(keys, n, r, keys[r], r + 1) >
+                                                     delta(keys, n, l - 1, keys[l - 1], l));
+      const int64_t p = left ? r : l - 1;
+      const int side = left ? 0 : 1;
+      store_child(nodes + p, side, b, h);
+      reinterpret_cast<int32_t *>(nodes + p)[12 + side] = ref;
+      if (left) range_lo[p] = (int32_t)l;
+      else range_hi[p] = (int32_t)r;
+      if (p < c0 || p > c1 - 2) {
+        const uint32_t e = atomicAdd(frontier_count, 1u);
+        if (e < frontier_cap) frontier[e] = (int32_t)p;
+        else atomicOr(&hdr->bad, 4);
+        break;
+      }
+      const uint32_t old = __hip_atomic_fetch_add(&s_cnt[p - c0], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      float sb[6];
+      int sh;
+      load_child(nodes + p, side ^ 1, sb, sh);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], sb[a]);
+        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+      }
+      h = (h > sh ? h : sh) + 1;
+      if (left) r = range_hi[p];
+      else l = range_lo[p];
+      ref = (int32_t)p;
+      if (l == 0 && r == n - 1) {
+        hdr->root = (int32_t)p;
+        hdr->height = h;
+        break;
+      }
+      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+  __syncthreads();
+  for (int64_t p = c0 + threadIdx.x; p < c1 && p < n - 1; p += kRefitThreads)
+    flags[p] = s_cnt[p - c0] == 1 ? 1u : 0u;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kRefitThreads) void k_agglo_top(const K *__restrict__ keys, int64_t n,
+                                                             NodeF32 *nodes, int32_t *range_lo,
+                                                             int32_t *range_hi, uint32_t *flags,
+                                                             TreeHeader *hdr,
+                                                             const int32_t *__restrict__ frontier,
+                                                             const uint32_t *__restrict__ frontier_count,
+                                                             uint32_t frontier_cap) {
+  const uint32_t cnt = min(*frontier_count, frontier_cap);
+  for (uint32_t e = threadIdx.x; e < cnt; e += kRefitThreads) {
+    int64_t p = frontier[e];
+    for (int step = 0; step < kRefitMaxSteps; ++step) {
+      const uint32_t old = __hip_atomic_fetch_add(flags + p, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      float b[6], sb[6];
+      int h, sh;
+      load_child(nodes + p, 0, b, h);
+      load_child(nodes + p, 1, sb, sh);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], sb[a]);
+        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+      }
+      h = (h > sh ? h : sh) + 1;
+      const int64_t l = range_lo[p], r = range_hi[p];
+      if (l == 0 && r == n - 1) {
+        hdr->root = (int32_t)p;
+        hdr->height = h;
+        break;
+      }
+      const bool left = l == 0 || (r != n - 1 && delta(keys, n, r, keys[r], r + 1) >
+                                                     delta(keys, n, l - 1, keys[l - 1], l));
+      const int64_t q = left ? r : l - 1;
+      const int side = left ? 0 : 1;
+      store_child(nodes + q, side, b, h);
+      reinterpret_cast<int32_t *>(nodes + q)[12 + side] = (int32_t)p;
+      if (left) range_lo[q] = (int32_t)l;
+      else range_hi[q] = (int32_t)r;
+      p = q;
+      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+}
+
+// at most two arrivals per split between chunks
+size_t agglo_frontier_cap(int64_t n) {
+  return (size_t)(2 * ((n + kRefitChunk - 1) / kRefitChunk) + 64);
+}
+
 // frontier entries: a crossing node has at most two, and every crossing node
 // lies on the root path of some chunk boundary
 size_t refit_frontier_cap(int64_t n) {
@@ -522,6 +666,50 @@ abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, const TreeH
     });
   return launch("quantise", s, [&] {
     k_quantise<ABX_PRIM_BOXES><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, dst);
+  });
+}
+
+abx_status launch_agglo(bool wide, int kind, bool q16, const void *keys, const float *prims,
+                        const int32_t *perm, int64_t n, NodeF32 *nodes, int32_t *range_lo,
+                        int32_t *range_hi, uint32_t *flags, TreeHeader *hdr, void *q16_leaves,
+                        int32_t *frontier, uint32_t *frontier_count, hipStream_t s) {
+  if (n == 0) return ABX_OK;
+  const unsigned g = grid_for(n, kRefitChunk);
+  const uint32_t cap = (uint32_t)agglo_frontier_cap(n);
+  ABX_TRY(fill_u32(frontier_count, 0, 1, s));
+#define ABX_AGG(KT, KD, QQ)                                                                       \
+  ABX_TRY(launch("agglo", s, [&] {                                                               \
+    k_agglo_local<KT, KD, QQ><<<g, kRefitThreads, 0, s>>>(static_cast<const KT *>(keys), prims,  \
+                                                          perm, n, nodes, range_lo, range_hi,    \
+                                                          flags, hdr, q16_leaves, frontier,      \
+                                                          frontier_count, cap);                  \
+  }))
+#define ABX_AGG_KIND(KT)                                                 \
+  if (kind == ABX_PRIM_POINTS) {                                         \
+    if (q16) ABX_AGG(KT, ABX_PRIM_POINTS, true);                         \
+    else ABX_AGG(KT, ABX_PRIM_POINTS, false);                            \
+  } else {                                                               \
+    if (q16) ABX_AGG(KT, ABX_PRIM_BOXES, true);                          \
+    else ABX_AGG(KT, ABX_PRIM_BOXES, false);                             \
+  }
+  if (wide) {
+    ABX_AGG_KIND(uint64_t)
+  } else {
+    ABX_AGG_KIND(uint32_t)
+  }
+#undef ABX_AGG_KIND
+#undef ABX_AGG
+  if (n <= kRefitChunk) return ABX_OK;
+  if (wide)
+    return launch("agglo_top", s, [&] {
+      k_agglo_top<uint64_t><<<1, kRefitThreads, 0, s>>>(static_cast<const uint64_t *>(keys), n, nodes,
+                                                        range_lo, range_hi, flags, hdr, frontier,
+                                                        frontier_count, cap);
+    });
+  return launch("agglo_top", s, [&] {
+    k_agglo_top<uint32_t><<<1, kRefitThreads, 0, s>>>(static_cast<const uint32_t *>(keys), n, nodes,
+                                                      range_lo, range_hi, flags, hdr, frontier,
+                                                      frontier_count, cap);
   });
 }
 

@@ -46,6 +46,9 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
   __shared__ int32_t s_stack[kLdsDepthSpatial * kTravBlock];
   const int64_t tq = xcd_tile(blockIdx.x, gridDim.x) * kTravBlock + threadIdx.x;
   if (tq >= qa.m) return;
+  // the fill pass of the one-pass scheme runs only after an overflow, and
+  // only when the caller's index buffer holds every hit
+  if (MODE == MODE_FILL && qa.flag && (qa.flag[0] == 0 || *qa.total > qa.capacity)) return;
   const int64_t qi = qa.order ? qa.order[tq] : tq;
   SpatialQuery<PRED> q;
   if (PRED == ABX_PRED_WITHIN) {
@@ -62,8 +65,12 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
       q.b[a] = p[3 + a];
     }
   }
-  int32_t *out = MODE == MODE_FILL ? indices + offsets[qi] : nullptr;
-  const int32_t row_len = MODE == MODE_FILL ? offsets[qi + 1] - offsets[qi] : 0;
+  int32_t *out = MODE == MODE_FILL    ? indices + offsets[qi]
+                 : MODE == MODE_STORE ? qa.buf + tq * qa.bufsize
+                                      : nullptr;
+  const int32_t row_len = MODE == MODE_FILL    ? offsets[qi + 1] - offsets[qi]
+                          : MODE == MODE_STORE ? qa.bufsize
+                                               : 0;
   int32_t cnt = 0, visited = 0, leaf_reads = 0;
 
   // a leaf child (primitive idx) whose node-stored box passed: confirm where
@@ -75,7 +82,7 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
       if (MODE == MODE_STATS) ++leaf_reads;
       if (!q.test(b)) return;
     }
-    if (MODE == MODE_FILL && cnt < row_len) out[cnt] = idx;
+    if ((MODE == MODE_FILL || MODE == MODE_STORE) && cnt < row_len) out[cnt] = idx;
     ++cnt;
   };
 
@@ -86,7 +93,7 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
     int32_t ovf[kMaxDepth];
     ABX_LDS int32_t *lds = (ABX_LDS int32_t *)(s_stack) + threadIdx.x;
     int sp = 0, nl = 0;
-    int32_t node = 0;
+    int32_t node = t.root;
     // a tree has n-1 internal nodes, each visited at most once: the bound
     // only guarantees termination
     for (int64_t it = 0; it < t.n; ++it) {
@@ -110,7 +117,8 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
       }
     }
   }
-  if (MODE == MODE_COUNT) out_counts[qi] = cnt;
+  if (MODE == MODE_COUNT || MODE == MODE_STORE) out_counts[qi] = cnt;
+  if (MODE == MODE_STORE && cnt > qa.bufsize) atomicOr(qa.flag, 1u);
   if (MODE == MODE_STATS) {
     out_counts[2 * qi] = visited;
     out_counts[2 * qi + 1] = leaf_reads;
@@ -176,6 +184,7 @@ TreeArgs tree_args(const abx_bvh *b) {
   t.nodes = b->nodes();
   t.leaves = b->leaves();
   t.n = b->n;
+  t.root = b->root;
   for (int a = 0; a < 6; ++a) t.scene[a] = b->scene[a];
   for (int a = 0; a < 3; ++a) {
     t.qo[a] = b->q_origin[a];
@@ -201,11 +210,15 @@ abx_status spatial_fmt(const abx_bvh *b, const QueryArgs &qa, int mode, int32_t 
                        const int32_t *offsets, int32_t *indices, hipStream_t s) {
   const TreeArgs t = tree_args(b);
   const unsigned g = grid_for(qa.m, kTravBlock);
-  const char *name = mode == MODE_COUNT ? "spatial_count" : mode == MODE_FILL ? "spatial_fill"
-                                                                              : "spatial_stats";
+  const char *name = mode == MODE_COUNT  ? "spatial_count"
+                     : mode == MODE_FILL  ? "spatial_fill"
+                     : mode == MODE_STORE ? "spatial_store"
+                                          : "spatial_stats";
   return launch(name, s, [&] {
     if (mode == MODE_COUNT)
       k_spatial<KIND, PRED, FMT, MODE_COUNT><<<g, kTravBlock, 0, s>>>(t, qa, counts, offsets, indices);
+    else if (mode == MODE_STORE)
+      k_spatial<KIND, PRED, FMT, MODE_STORE><<<g, kTravBlock, 0, s>>>(t, qa, counts, offsets, indices);
     else if (mode == MODE_FILL)
       k_spatial<KIND, PRED, FMT, MODE_FILL><<<g, kTravBlock, 0, s>>>(t, qa, counts, offsets, indices);
     else
@@ -223,9 +236,17 @@ abx_status spatial_pred(const abx_bvh *b, const QueryArgs &qa, int mode, int32_t
 
 abx_status launch_spatial(const abx_bvh *b, int pred, const float *data, int64_t m,
                           const float *radii, float radius, const int32_t *order, int mode,
-                          int32_t *counts, const int32_t *offsets, int32_t *indices, hipStream_t s) {
+                          int32_t *counts, const int32_t *offsets, int32_t *indices, hipStream_t s,
+                          const OnePass *op) {
   if (m == 0) return ABX_OK;
-  QueryArgs qa{data, m, radii, radius, order};
+  QueryArgs qa{data, m, radii, radius, order, nullptr, 0, nullptr, nullptr, 0};
+  if (op) {
+    qa.buf = op->buf;
+    qa.bufsize = op->bufsize;
+    qa.flag = op->flag;
+    qa.total = op->total;
+    qa.capacity = op->capacity;
+  }
   if (b->kind == ABX_PRIM_POINTS) {
     if (pred == ABX_PRED_WITHIN)
       return spatial_pred<ABX_PRIM_POINTS, ABX_PRED_WITHIN>(b, qa, mode, counts, offsets, indices, s);
@@ -234,6 +255,53 @@ abx_status launch_spatial(const abx_bvh *b, int pred, const float *data, int64_t
   if (pred == ABX_PRED_WITHIN)
     return spatial_pred<ABX_PRIM_BOXES, ABX_PRED_WITHIN>(b, qa, mode, counts, offsets, indices, s);
   return spatial_pred<ABX_PRIM_BOXES, ABX_PRED_INTERSECTS_BOX>(b, qa, mode, counts, offsets, indices, s);
+}
+
+// ------------------------------------------------------------ 1P compaction
+// After a storing pass with no overflow: slot j of the row stored for sorted
+// position tq goes to indices[offsets[q] + j] when j < count[q] (one thread
+// per buffer slot, so the buffer is read in order).
+__global__ __launch_bounds__(kTravBlock) void k_spatial_compact(const int32_t *__restrict__ buf,
+                                                                int32_t bufsize, int64_t m,
+                                                                const int32_t *__restrict__ order,
+                                                                const int32_t *__restrict__ counts,
+                                                                const int32_t *__restrict__ offsets,
+                                                                int32_t *__restrict__ indices,
+                                                                const uint32_t *__restrict__ flag,
+                                                                const int64_t *__restrict__ total,
+                                                                int64_t capacity) {
+  if (flag[0] != 0 || *total > capacity) return;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= m * bufsize) return;
+  const int64_t tq = id / bufsize, j = id - tq * bufsize;
+  const int64_t qi = order ? order[tq] : tq;
+  if (j < counts[qi]) indices[offsets[qi] + j] = buf[id];
+}
+
+// info[0] = status, info[1] = traversals made
+__global__ void k_spatial_1p_info(const uint32_t *__restrict__ flag, const int64_t *__restrict__ total,
+                                  int64_t capacity, int64_t max_count, int32_t *__restrict__ info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t t = *total;
+  const bool fits = t <= capacity;
+  info[0] = t >= max_count ? ABX_ERR_OVERFLOW : (fits ? ABX_OK : ABX_ERR_CAPACITY);
+  info[1] = flag[0] != 0 && fits ? 2 : 1;
+}
+
+abx_status launch_spatial_compact(const OnePass &op, int64_t m, const int32_t *order,
+                                  const int32_t *counts, const int32_t *offsets, int32_t *indices,
+                                  int32_t *info, int64_t max_count, hipStream_t s) {
+  if (m > 0) {
+    const int64_t slots = m * (int64_t)op.bufsize;
+    const unsigned g = (unsigned)((slots + kTravBlock - 1) / kTravBlock);
+    ABX_TRY(launch("spatial_compact", s, [&] {
+      k_spatial_compact<<<g, kTravBlock, 0, s>>>(op.buf, op.bufsize, m, order, counts, offsets,
+                                                 indices, op.flag, op.total, op.capacity);
+    }));
+  }
+  return launch("spatial_1p_info", s, [&] {
+    k_spatial_1p_info<<<1, 64, 0, s>>>(op.flag, op.total, op.capacity, max_count, info);
+  });
 }
 
 struct NearestScratch {

@@ -24,6 +24,7 @@ struct TreeArgs {
   const void *nodes;
   const void *leaves;
   int64_t n;
+  int32_t root;            // internal node at the root (n >= 2)
   float scene[6];
   float qo[3], qs[3];
   const float *scene_dev;  // the same scene box in device memory
@@ -47,6 +48,12 @@ struct QueryArgs {
   const float *radii;
   float radius;
   const int32_t *order;  // sorted position -> caller's query index (or null)
+  // one-pass (1P) scheme only
+  int32_t *buf;          // [m * bufsize] stored hits, one row per sorted position
+  int32_t bufsize;
+  uint32_t *flag;        // [0] != 0: some query found more than bufsize hits
+  const int64_t *total;  // device total of the scanned counts
+  int64_t capacity;      // entries the caller's index buffer holds
 };
 
 // hardware dispatches workgroup b to XCD b % 8; hand XCD x a contiguous
@@ -181,7 +188,7 @@ __device__ __forceinline__ void stack_pop2(ABX_LDS int32_t *ln, ABX_LDS float *l
   }
 }
 
-enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_STATS = 2 };
+enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_STATS = 2, MODE_STORE = 3 };
 
 // ------------------------------------------------------------------ nearest
 // A candidate (squared distance d, primitive index i) packed into one
@@ -320,7 +327,7 @@ struct PlainMap {
   int k;
   __device__ __forceinline__ QInfo info(int64_t qi, const TreeArgs &t) const {
     QInfo r;
-    r.root = t.n == 1 ? ~0 : 0;
+    r.root = t.n == 1 ? ~0 : t.root;
     r.kk = k;
     r.out = qi * k;
     r.base = 0;

@@ -149,3 +149,22 @@ def test_forest_sizes_validation():
     pr = abx.ForestPrimitives(513, off.ctypes.data, 1, 1, 0)  # too many trees
     assert L.abx_forest_build_sizes(C.byref(pr), C.byref(tb), C.byref(sb)) == abx.ERR_INVALID_ARG
     assert L.abx_graph_begin(None) == abx.ERR_INVALID_ARG     # null stream cannot be captured
+
+
+def test_onepass_validation_without_gpu():
+    abx, L = _lib()
+    sb = C.c_size_t()
+    pr = abx.Predicates(0, 1, 10, None, 1.0, 1)
+    assert L.abx_query_spatial_1p_sizes(None, C.byref(pr), 4, C.byref(sb)) == abx.ERR_INVALID_ARG
+    info = C.c_void_p(1)
+    assert L.abx_query_spatial_1p(None, C.byref(pr), 4, None, 0, None, None, 0, info, None) == \
+        abx.ERR_INVALID_ARG
+
+
+def test_build_rejects_unknown_hierarchy():
+    abx, L = _lib()
+    tb, sb = C.c_size_t(), C.c_size_t()
+    ok = abx.Primitives(abx.PRIM_POINTS, 1, 5)
+    for h, want in ((0, abx.OK), (1, abx.OK), (2, abx.ERR_INVALID_ARG), (-1, abx.ERR_INVALID_ARG)):
+        opt = abx.BuildOptions(abx.NODES_FP32, 21, h)
+        assert L.abx_bvh_build_sizes(C.byref(ok), C.byref(opt), C.byref(tb), C.byref(sb)) == want
