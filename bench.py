@@ -36,6 +36,7 @@ def parse():
                     choices=["C1", "C2", "C3", "C4", "C5", "COPY", "PAPER"])
     ap.add_argument("--nodes", default="q16", choices=["fp32", "q16"])
     ap.add_argument("--morton-bits", type=int, default=21)
+    ap.add_argument("--hierarchy", default="karras", choices=["karras", "agglomerative"])
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -48,6 +49,28 @@ def parse():
     ap.add_argument("--paper-sizes", default="1e4,1e5,1e6,1e7",
                     help="m = n sweep of the paper's filled and hollow cases (PAPER)")
     return ap.parse_args()
+
+
+def measured_traffic(kernel, workload, nodes, k):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), or None when no
+    summary covers this launch or the kernel sources changed since."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        with open(path) as f:
+            rec = json.load(f)
+        if (rec.get("kernel"), rec.get("workload"), rec.get("nodes"), rec.get("k")) != \
+                (kernel, workload, nodes, k):
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None, None
+        return int(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
 
 
 def algorithmic_bytes(stats, node_b, leaf_b, per_query_fixed):
@@ -99,7 +122,8 @@ def main():
     def step(rec=None):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if rec is not None else None
         if e: e[0].record()
-        t = abx.bvh_build(pts, node_format=args.nodes, morton_bits=args.morton_bits)
+        t = abx.bvh_build(pts, node_format=args.nodes, morton_bits=args.morton_bits,
+                          hierarchy=args.hierarchy)
         if e: e[1].record()
         off, idx = abx.query_spatial(t, qs, radius=r, capacity=rec.get("cap") if rec else None)
         if e: e[2].record()
@@ -132,7 +156,8 @@ def main():
     step_ms = phases.sum(axis=1)
     build_ms, rad_ms, knn_ms = np.median(phases, axis=0)
 
-    kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_top", "quantise",
+    kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_top", "agglo",
+               "agglo_top", "quantise",
                "scene_partial", "query_codes", "spatial_count", "spatial_fill", "scan_tiles", "nearest",
                "nearest_coop"]
     ktimes = {}
@@ -166,9 +191,10 @@ def main():
     if dom in alg:
         per_launch = alg[dom]
         achieved = per_launch / (ktimes[dom]["ms_per_launch"] * 1e-3) / 1e9
+        traffic, tsrc = measured_traffic(dom, args.workload, args.nodes, k)
         roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    bytes_per_launch=per_launch,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    traffic_source=tsrc, bytes_per_launch=per_launch,
                     ms_per_launch=round(ktimes[dom]["ms_per_launch"], 4))
     else:
         roof = dict(kernel=dom, bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s",
@@ -184,6 +210,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['desc']}", "n": n, "m": m, "k": k,
                    "radius": r, "nodes": args.nodes, "morton_bits": args.morton_bits,
+                   "hierarchy": args.hierarchy,
                    "parallelism": "single GPU"},
         "build_mprims_s": round(n / (build_ms * 1e-3) / 1e6, 1),
         "radius_qps": round(m / (rad_ms * 1e-3), 1),
