@@ -8,8 +8,9 @@
  *     codes, sort, Karras hierarchy, bottom-up internal boxes;
  *   - traversal (section 2.2): spatial queries by an iterative stack
  *     traversal with count-then-fill (2P) output, nearest queries by a stack
- *     traversal that visits the nearer child first and stops when no
- *     remaining candidate can improve, query ordering by Morton code;
+ *     traversal that visits the nearer child first (nearer by box centre
+ *     here) and stops when no remaining candidate can improve, query
+ *     ordering by Morton code;
  *   - interface (section 2.3): build from primitives, query with a batch of
  *     predicates, results as CSR offsets + indices.
  *
@@ -229,7 +230,7 @@ abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, 
  * frontier is split among the lanes, their pruning bound is shared, their
  * candidate lists are merged exactly).  Results do not depend on the value.
  * abx_set_nearest_budget sets the process-wide budget (<= 0: unlimited, i.e.
- * one lane per query throughout) and returns the previous one.  Default 16384.
+ * one lane per query throughout) and returns the previous one.  Default 32768.
  * A batch of m queries uses min(budget, max(512, m / 16)): small batches
  * leave the GPU idle and hand heavy queries to whole wavefronts sooner. */
 int64_t abx_set_nearest_budget(int64_t visits);

@@ -344,7 +344,7 @@ abx_status abx_forest_autotune(abx_forest *f, const abx_forest_queries *q, int32
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int bpcs[] = {2, 4, 6, 8};
   const int grabs[] = {1, 4};
-  const int64_t budgets[] = {4096, 16384, 65536};
+  const int64_t budgets[] = {8192, 32768, 131072};
   hipEvent_t a, b;
   ABX_HIP(hipEventCreate(&a));
   ABX_HIP(hipEventCreate(&b));

@@ -11,8 +11,10 @@
 // the second one deferred on the stack).  Count pass and fill pass (2P).
 //
 // Nearest (section 2.2 "Traversal for nearest queries"): the same stack walk
-// where the nearer child is visited first and the farther one deferred with
-// its distance; a node is pruned when its box is strictly farther than the
+// where one child is visited first and the other deferred with its box
+// distance (the paper puts the nearer box first; here the child whose box
+// centre is nearer goes first, which fills the list sooner); a node is
+// pruned when its box is strictly farther than the
 // current k-th candidate, which is how the walk stops once the remaining
 // candidates cannot improve the result.  The k best candidates are kept
 // sorted in registers by (squared distance, index).
