@@ -295,12 +295,14 @@ __device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &
     // around a curved or slanted patch reaches far in front of it); the
     // centre tracks the primitives better, so the list fills with near
     // candidates sooner and prunes more (C3: 16 % fewer visits).
+    // (lo - q) - (q - hi) = 2 (centre - q), from the differences the box
+    // distances already formed
     float cl = 0.0f, cr = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const float qa = a == 0 ? q.x : (a == 1 ? q.y : q.z);
-      const float ml = 0.5f * (c.l[a] + c.l[3 + a]) - qa;
-      const float mr = 0.5f * (c.r[a] + c.r[3 + a]) - qa;
+      const float ml = (c.l[a] - qa) - (qa - c.l[3 + a]);
+      const float mr = (c.r[a] - qa) - (qa - c.r[3 + a]);
       cl = __fmaf_rn(ml, ml, cl);
       cr = __fmaf_rn(mr, mr, cr);
     }
