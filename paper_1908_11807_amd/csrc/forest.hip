@@ -349,7 +349,7 @@ abx_status forest_launch_rows(const int64_t *poff, const int64_t *qoff, const in
   });
 }
 
-int coop_grid();
+int coop_grid(int waves);
 int device_cus();
 
 template <int KIND, int FMT, int K>
@@ -362,8 +362,9 @@ abx_status forest_nearest_k(const TreeArgs &t, const ForestMap &map, const float
                                                              heavy, queue, grab);
   }));
   return launch("forest_nearest_coop", s, [&] {
-    k_nearest_coop<KIND, FMT, K, ForestMap><<<(unsigned)coop_grid(), kWave, 0, s>>>(t, map, pts, idx,
-                                                                                   dist, heavy);
+    k_nearest_coop<KIND, FMT, K, ForestMap, coop_waves(K)>
+        <<<(unsigned)coop_grid(coop_waves(K)), CoopShape<coop_waves(K)>::kThreads, 0, s>>>(
+            t, map, pts, idx, dist, heavy);
   });
 }
 

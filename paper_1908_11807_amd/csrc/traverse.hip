@@ -320,7 +320,9 @@ int device_cus() {
   return cus > 0 ? cus : 256;
 }
 
-int coop_grid() { return device_cus() * kCoopBlocksPerCU; }
+// persistent grid of the cooperative pass: as many workgroups as fit at once
+// (LDS bound: a W-wavefront workgroup takes 8 KB per wavefront)
+int coop_grid(int waves) { return device_cus() * std::max(1, 16 / waves); }
 
 template <int KIND, int FMT, int K>
 abx_status nearest_k(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order, int k,
@@ -340,9 +342,11 @@ abx_status nearest_k(const abx_bvh *b, const float *pts, int64_t m, const int32_
     k_nearest<KIND, FMT, K, false><<<g, kTravBlock, 0, s>>>(t, map, pts, m, order, idx, dist,
                                                             stats, ns.budget, heavy);
   }));
-  const unsigned g2 = (unsigned)coop_grid();
+  constexpr int W = coop_waves(K);
+  const unsigned g2 = (unsigned)coop_grid(W);
   return launch("nearest_coop", s, [&] {
-    k_nearest_coop<KIND, FMT, K, PlainMap><<<g2, kWave, 0, s>>>(t, map, pts, idx, dist, heavy);
+    k_nearest_coop<KIND, FMT, K, PlainMap, W>
+        <<<g2, CoopShape<W>::kThreads, 0, s>>>(t, map, pts, idx, dist, heavy);
   });
 }
 

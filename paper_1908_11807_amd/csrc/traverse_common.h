@@ -17,8 +17,6 @@ constexpr int kLdsDepthNearest = 8;
 // Occupancy target of the one-lane nearest pass: 8 waves per SIMD fit the
 // register budget (64 VGPRs) up to k = 10; the k = 32 list alone takes 64.
 constexpr int nearest_waves_per_eu(int K) { return K > 16 ? 4 : (K > 10 ? 6 : 8); }
-// the cooperative pass keeps a few more registers per lane (frontier work)
-constexpr int coop_waves_per_eu(int K) { return K > 16 ? 3 : 5; }
 
 struct TreeArgs {
   const void *nodes;
@@ -433,129 +431,159 @@ __device__ __forceinline__ float wave_min(float v) {
   return v;
 }
 
-constexpr int kCoopFront = 256;     // frontier size at which the lanes split up
-constexpr int kCoopFrontCap = 512;  // >= 2 * (kCoopFront - 1): one expansion's output
-constexpr int kCoopWindow = kCoopFrontCap / kWave;  // LDS stack entries per lane
-constexpr int kCoopBlocksPerCU = 4 * coop_waves_per_eu(1);
+// wavefronts per heavy query: 16 (the heaviest query of a batch bounds the
+// launch, so its walk is split 1024 ways); 8 for k > 16, whose lists need
+// more registers than a 1024-thread workgroup leaves per lane
+constexpr int coop_waves(int K) { return K > 16 ? 8 : 16; }
 
-// Pass 2: one wavefront per heavy query (several lanes per query).  The wave
-// expands the tree breadth-first until the frontier holds kCoopFront nodes,
-// then lane l walks frontier entries l, l+64, ... depth-first with its own
-// stack and candidate list.  Every step the lanes share the smallest of
-// their k-th distances (each is the k-th distance of k real primitives, so
+// Pass 2: a workgroup of W wavefronts per heavy query.  The launch lasts as
+// long as its heaviest query, whose walk is split W*64 ways.  The workgroup
+// expands the tree breadth-first until the frontier holds 256*W nodes, then
+// thread i walks frontier entries i, i + 64W, ... depth-first with its own
+// stack and candidate list.  The threads share the smallest of their k-th
+// distances through LDS (each is the k-th distance of k real primitives, so
 // it bounds the final k-th distance from above) and prune with it.  Every
-// primitive of the final result lives in the list of the lane that met it,
-// so the k best of the 64 lists, taken in (distance, index) order, are the
-// exact answer.  Runs as a persistent grid draining the heavy list.
-template <int KIND, int FMT, int K, class Map>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(coop_waves_per_eu(K))))
-void k_nearest_coop(TreeArgs t, Map map,
-                                                        const float *__restrict__ pts,
-                                                        int32_t *__restrict__ indices,
-                                                        float *__restrict__ dist, HeavyList heavy) {
+// primitive of the final result lives in the list of the thread that met it,
+// so the k best of all lists, taken in (distance, index) order, are the
+// exact answer: each wavefront merges its 64 lists, then the first merges
+// the W results.  Runs as a persistent grid draining the heavy list.
+template <int W>
+struct CoopShape {
+  static constexpr int kThreads = W * kWave;
+  static constexpr int kFront = 256 * W;     // frontier size at which the threads split up
+  static constexpr int kCap = 2 * kFront;    // >= 2 * (kFront - 1): one expansion's output
+  static constexpr int kWindow = kCap / kThreads;  // LDS stack entries per thread
+};
+
+// LDS float minimum through the unsigned bit pattern (values are >= 0)
+__device__ __forceinline__ void lds_min(uint32_t *p, float v) {
+  atomicMin(p, __float_as_uint(v));
+}
+
+template <int KIND, int FMT, int K, class Map, int W>
+__global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
+    TreeArgs t, Map map, const float *__restrict__ pts, int32_t *__restrict__ indices,
+    float *__restrict__ dist, HeavyList heavy) {
+  using S = CoopShape<W>;
   // two frontier buffers; during the depth-first phase the one not holding
-  // the final frontier is the lanes' stack window
-  __shared__ int32_t s_fn[2][kCoopFrontCap];
-  __shared__ float s_fd[2][kCoopFrontCap];
-  const int lane = threadIdx.x;
+  // the final frontier is the threads' stack window
+  __shared__ int32_t s_fn[2][S::kCap];
+  __shared__ float s_fd[2][S::kCap];
+  __shared__ int64_t s_best[W][K];
+  __shared__ uint32_t s_size[2], s_bound, s_h;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const uint32_t total = heavy.count[0];
   resolve_qframe(t);
   int32_t reads = 0;
   while (true) {
-    __syncthreads();  // the previous query's stack window is free again
-    uint32_t h = 0;
-    if (lane == 0) h = atomicAdd(heavy.count + 1, 1u);
-    h = __shfl(h, 0, kWave);
+    __syncthreads();  // the previous query's buffers are free again
+    if (tid == 0) s_h = atomicAdd(heavy.count + 1, 1u);
+    __syncthreads();
+    const uint32_t h = s_h;
     if (h >= total) break;
     const int32_t qi = heavy.q[h];
     const QInfo info = map.info(qi, t);
     const int k = info.kk;
     const KnnQuery q{pts[3 * (int64_t)qi], pts[3 * (int64_t)qi + 1], pts[3 * (int64_t)qi + 2]};
-    float bound = heavy.bound[h];
     KnnList<K> L;
     L.init(k);
+    if (tid == 0) {
+      s_fn[0][0] = info.root;
+      s_fd[0][0] = 0.0f;
+      s_bound = __float_as_uint(heavy.bound[h]);
+    }
+    __syncthreads();
 
     // breadth-first expansion of the frontier
     int cur = 0, fsize = 1;
-    if (lane == 0) {
-      s_fn[0][0] = info.root;
-      s_fd[0][0] = 0.0f;
-    }
-    __syncthreads();
-    while (fsize > 0 && fsize < kCoopFront) {
-      int nsize = 0;
-      for (int base = 0; base < fsize; base += kWave) {
-        const int e = base + lane;
+    while (fsize > 0 && fsize < S::kFront) {
+      // the size of the next frontier counts into s_size[cur ^ 1], last read
+      // before the previous level's closing barrier
+      if (tid == 0) s_size[cur ^ 1] = 0;
+      __syncthreads();
+      const float bnd = __uint_as_float(s_bound);
+      for (int base = 0; base < fsize; base += S::kThreads) {
+        const int e = base + tid;
         bool el = false, er = false;
         int32_t lref = 0, rref = 0;
         float dl = 0.0f, dr = 0.0f;
-        if (e < fsize && s_fd[cur][e] <= fminf(L.kth(), bound)) {
+        if (e < fsize && s_fd[cur][e] <= fminf(L.kth(), bnd)) {
           Kids c;
           load_kids<KIND, FMT>(t, s_fn[cur][e], c);
           dl = box_dist2(c.l[0], c.l[1], c.l[2], c.l[3], c.l[4], c.l[5], q.x, q.y, q.z);
           dr = box_dist2(c.r[0], c.r[1], c.r[2], c.r[3], c.r[4], c.r[5], q.x, q.y, q.z);
-          if (c.lref < 0) knn_leaf<KIND, FMT, K>(t, q, ~c.lref, dl, fminf(L.kth(), bound), L, reads);
-          if (c.rref < 0) knn_leaf<KIND, FMT, K>(t, q, ~c.rref, dr, fminf(L.kth(), bound), L, reads);
-          const float thr = fminf(L.kth(), bound);
+          if (c.lref < 0) knn_leaf<KIND, FMT, K>(t, q, ~c.lref, dl, fminf(L.kth(), bnd), L, reads);
+          if (c.rref < 0) knn_leaf<KIND, FMT, K>(t, q, ~c.rref, dr, fminf(L.kth(), bnd), L, reads);
+          const float thr = fminf(L.kth(), bnd);
           el = c.lref >= 0 && dl <= thr;
           er = c.rref >= 0 && dr <= thr;
           lref = c.lref;
           rref = c.rref;
         }
+        // wave-level compaction, one LDS reservation per wave
         const uint64_t bl = __ballot(el), br = __ballot(er);
-        const int cl = __popcll(bl);
+        const int cl = __popcll(bl), cnt = cl + __popcll(br);
+        uint32_t o = 0;
+        if (lane == 0 && cnt > 0) o = atomicAdd(&s_size[cur ^ 1], (uint32_t)cnt);
+        o = __shfl(o, 0, kWave);
         if (el) {
-          const int o = nsize + __popcll(bl & lt);
-          s_fn[cur ^ 1][o] = lref;
-          s_fd[cur ^ 1][o] = dl;
+          const int at = (int)o + __popcll(bl & lt);
+          s_fn[cur ^ 1][at] = lref;
+          s_fd[cur ^ 1][at] = dl;
         }
         if (er) {
-          const int o = nsize + cl + __popcll(br & lt);
-          s_fn[cur ^ 1][o] = rref;
-          s_fd[cur ^ 1][o] = dr;
+          const int at = (int)o + cl + __popcll(br & lt);
+          s_fn[cur ^ 1][at] = rref;
+          s_fd[cur ^ 1][at] = dr;
         }
-        nsize += cl + __popcll(br);
-        bound = wave_min(fminf(bound, L.kth()));
       }
+      const float wm = wave_min(L.kth());
+      if (lane == 0) lds_min(&s_bound, wm);
       __syncthreads();
       cur ^= 1;
-      fsize = nsize;
+      fsize = (int)s_size[cur];
     }
 
-    // depth-first walks of the lane's share of the frontier
+    // depth-first walks of the thread's share of the frontier
     int32_t ovf_n[kMaxDepth];
     float ovf_d[kMaxDepth];
-    ABX_LDS int32_t *lds_n = (ABX_LDS int32_t *)(s_fn[cur ^ 1]) + lane;
-    ABX_LDS float *lds_d = (ABX_LDS float *)(s_fd[cur ^ 1]) + lane;
+    ABX_LDS int32_t *lds_n = (ABX_LDS int32_t *)(s_fn[cur ^ 1]) + tid;
+    ABX_LDS float *lds_d = (ABX_LDS float *)(s_fd[cur ^ 1]) + tid;
     int sp = 0, nl = 0;
-    const int mine = fsize > lane ? (fsize - 1 - lane) / kWave + 1 : 0;
+    const int mine = fsize > tid ? (fsize - 1 - tid) / S::kThreads + 1 : 0;
     for (int a = mine - 1; a >= 0; --a)
-      stack_push2<kCoopWindow, kWave>(lds_n, lds_d, ovf_n, ovf_d, sp, nl,
-                                      s_fn[cur][lane + kWave * a], s_fd[cur][lane + kWave * a]);
+      stack_push2<S::kWindow, S::kThreads>(lds_n, lds_d, ovf_n, ovf_d, sp, nl,
+                                           s_fn[cur][tid + S::kThreads * a],
+                                           s_fd[cur][tid + S::kThreads * a]);
     __syncthreads();
     bool active = true;
     int32_t node = -1;
+    float bound = __uint_as_float(s_bound);
     for (int64_t it = 0; it < 4 * t.n + 64; ++it) {
-      bound = wave_min(fminf(bound, L.kth()));
+      // share the workgroup's bound: one LDS atomic per wave and step
+      const float wm = wave_min(fminf(bound, L.kth()));
+      if (lane == 0) lds_min(&s_bound, wm);
+      bound = fminf(wm, __uint_as_float(s_bound));
       if (!__any(active)) break;
       if (active) {
         if (node < 0)
-          node = knn_pop<kWave, kCoopWindow>(fminf(L.kth(), bound), lds_n, lds_d, ovf_n, ovf_d,
-                                             sp, nl);
+          node = knn_pop<S::kThreads, S::kWindow>(fminf(L.kth(), bound), lds_n, lds_d, ovf_n,
+                                                  ovf_d, sp, nl);
         if (node < 0) {
           active = false;
         } else {
-          node = knn_visit<KIND, FMT, K, kWave, kCoopWindow>(t, q, node, bound, L, lds_n, lds_d,
-                                                             ovf_n, ovf_d, sp, nl, reads);
+          node = knn_visit<KIND, FMT, K, S::kThreads, S::kWindow>(t, q, node, bound, L, lds_n,
+                                                                  lds_d, ovf_n, ovf_d, sp, nl,
+                                                                  reads);
         }
       }
     }
 
-    // merge: k rounds of a wave-wide (distance, index) minimum over the
-    // lanes' list fronts
-    for (int s = 0; s < K - k; ++s) L.shift();
-    int64_t out = 0;
+    // merge: each wave takes the k best of its 64 lists (k rounds of a
+    // wave-wide minimum over the list fronts), then wave 0 the k best of the
+    // W wave results
+    for (int s2 = 0; s2 < K - k; ++s2) L.shift();
     for (int j = 0; j < k; ++j) {
       int64_t m = L.key[0];
 #pragma unroll
@@ -566,11 +594,45 @@ void k_nearest_coop(TreeArgs t, Map map,
       // keys are unique (one entry per primitive), so exactly one lane
       // holds the minimum
       if (L.key[0] == m) L.shift();
-      if (lane == j) out = m;
+      if (lane == 0) s_best[wv][j] = m;
     }
-    if (lane < k) {
-      indices[info.out + lane] = key_index(out) - info.base;
-      dist[info.out + lane] = sqrtf(key_dist(out));
+    __syncthreads();
+    if (wv == 0) {
+      // candidates c = lane, lane + 64, ... of the W*k wave results
+      constexpr int kPer = (W * K + kWave - 1) / kWave;
+      int64_t mine_c[kPer];
+#pragma unroll
+      for (int a = 0; a < kPer; ++a) {
+        const int c = lane + kWave * a;
+        mine_c[a] = c < W * k ? s_best[c / k][c % k] : kKeyEmpty;
+      }
+      int64_t out = 0;
+      for (int j = 0; j < k; ++j) {
+        int64_t lo = mine_c[0];
+        int at = 0;
+#pragma unroll
+        for (int a = 1; a < kPer; ++a)
+          if (mine_c[a] < lo) {
+            lo = mine_c[a];
+            at = a;
+          }
+        int64_t m = lo;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+          const int64_t m2 = __shfl_xor(m, o, kWave);
+          m = m2 < m ? m2 : m;
+        }
+        if (lo == m) {
+#pragma unroll
+          for (int a = 0; a < kPer; ++a)
+            if (a == at) mine_c[a] = kKeyEmpty;
+        }
+        if (lane == j) out = m;
+      }
+      if (lane < k) {
+        indices[info.out + lane] = key_index(out) - info.base;
+        dist[info.out + lane] = sqrtf(key_dist(out));
+      }
     }
   }
   (void)reads;
