@@ -264,7 +264,7 @@ struct ForestMap {
 
 // occupancy target: the persistent loop keeps a few more values live than
 // the plain pass
-constexpr int forest_waves_per_eu(int K) { return K > 16 ? 2 : (K > 10 ? 4 : (K > 4 ? 6 : 8)); }
+constexpr int forest_waves_per_eu(int K) { return K > 16 ? 2 : (K > 10 ? 4 : (K > 4 ? 5 : 8)); }
 
 // Persistent pass 1 over every tree's queries: each wavefront takes
 // `grab` tiles of 64 Morton-ordered queries at a time from the queue.

@@ -14,9 +14,10 @@ constexpr int kMaxDepth = 128;
 constexpr int kLdsDepthSpatial = 16;
 constexpr int kLdsDepthNearest = 8;
 
-// Occupancy target of the one-lane nearest pass: 8 waves per SIMD fit the
-// register budget (64 VGPRs) up to k = 10; the k = 32 list alone takes 64.
-constexpr int nearest_waves_per_eu(int K) { return K > 16 ? 4 : (K > 10 ? 6 : 8); }
+// Occupancy target of the one-lane nearest pass (waves per SIMD).  Six beat
+// eight at k = 10 on the C3 shell (fewer walks competing for L2, no spills);
+// the k = 32 list alone takes 64 registers.
+constexpr int nearest_waves_per_eu(int K) { return K > 16 ? 3 : (K > 10 ? 4 : (K > 4 ? 6 : 8)); }
 
 struct TreeArgs {
   const void *nodes;
@@ -245,6 +246,42 @@ struct KnnList {
   }
 };
 
+// Candidates waiting to enter a lane's list.  Inserting one costs ~70 VALU
+// operations for k = 10, and a wavefront pays them whenever any of its lanes
+// inserts; a lane meets a qualifying leaf in a few percent of its steps, so
+// nearly every step paid for one lane.  Lanes therefore park up to two
+// candidates and the wavefront inserts them together once kDeferLanes lanes
+// have one waiting (a third candidate goes in at once).  Pruning meanwhile
+// uses the list's k-th distance without the parked candidates: an upper
+// bound of the final one, so nothing the exact walk needs is pruned.
+constexpr int kDeferLanes = 8;
+
+struct KnnPending {
+  int64_t a, b;
+  __device__ __forceinline__ void init() { a = b = kKeyEmpty; }
+  template <int K>
+  __device__ __forceinline__ void park(KnnList<K> &L, int64_t x) {
+    if (a == kKeyEmpty) a = x;
+    else if (b == kKeyEmpty) b = x;
+    else L.offer_key(x);
+  }
+  // called by every active lane of the wavefront
+  template <int K>
+  __device__ __forceinline__ void flush_some(KnnList<K> &L) {
+    if (__popcll(__ballot(a != kKeyEmpty)) >= kDeferLanes && a != kKeyEmpty) {
+      L.offer_key(a);
+      a = b;
+      b = kKeyEmpty;
+    }
+  }
+  template <int K>
+  __device__ __forceinline__ void flush_all(KnnList<K> &L) {
+    if (a != kKeyEmpty) L.offer_key(a);
+    if (b != kKeyEmpty) L.offer_key(b);
+    a = b = kKeyEmpty;
+  }
+};
+
 struct KnnQuery {
   float x, y, z;
 };
@@ -272,18 +309,29 @@ __device__ __forceinline__ void knn_leaf(const TreeArgs &t, const KnnQuery &q, i
 // return the nearer qualifying internal child (the farther one is pushed),
 // or -1 when neither qualifies.  `bound` is an external upper bound of the
 // final k-th distance (+inf when there is none).
-template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest>
+template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest, bool DEFER = false>
 __device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &q, int32_t node,
                                              float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
                                              ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
-                                             int &sp, int &nl, int32_t &reads) {
+                                             int &sp, int &nl, int32_t &reads,
+                                             KnnPending *pend = nullptr) {
   Kids c;
   load_kids<KIND, FMT>(t, node, c);
   const float dl = box_dist2(c.l[0], c.l[1], c.l[2], c.l[3], c.l[4], c.l[5], q.x, q.y, q.z);
   const float dr = box_dist2(c.r[0], c.r[1], c.r[2], c.r[3], c.r[4], c.r[5], q.x, q.y, q.z);
   const bool ll = c.lref < 0, lr = c.rref < 0;
-  if (ll) knn_leaf<KIND, FMT, K>(t, q, ~c.lref, dl, fminf(L.kth(), bound), L, reads);
-  if (lr) knn_leaf<KIND, FMT, K>(t, q, ~c.rref, dr, fminf(L.kth(), bound), L, reads);
+  if (DEFER && exact_leaf_slots<KIND, FMT>()) {
+    const float thr0 = fminf(L.kth(), bound);
+    const bool ol = ll && dl <= thr0, orr = lr && dr <= thr0;
+    if (ol || orr) {
+      pend->park(L, ol ? knn_key(dl, ~c.lref) : knn_key(dr, ~c.rref));
+      if (ol && orr) pend->park(L, knn_key(dr, ~c.rref));
+    }
+    pend->flush_some(L);
+  } else {
+    if (ll) knn_leaf<KIND, FMT, K>(t, q, ~c.lref, dl, fminf(L.kth(), bound), L, reads);
+    if (lr) knn_leaf<KIND, FMT, K>(t, q, ~c.rref, dr, fminf(L.kth(), bound), L, reads);
+  }
   const float thr = fminf(L.kth(), bound);
   const bool gl = !ll && dl <= thr, gr = !lr && dr <= thr;
   if (gl && gr) {
@@ -399,17 +447,20 @@ __device__ __forceinline__ void nearest_lane(const TreeArgs &t, const Map &map,
     int sp = 0, nl = 0;
     int32_t node = info.root;
     const int64_t limit = budget < t.n ? budget : t.n;
+    KnnPending pend;
+    pend.init();
     done = false;
     for (int64_t it = 0; it < limit; ++it) {
       if (STATS) ++visited;
-      node = knn_visit<KIND, FMT, K, B>(t, q, node, INFINITY, L, lds_n, lds_d, ovf_n, ovf_d, sp,
-                                        nl, reads);
+      node = knn_visit<KIND, FMT, K, B, kLdsDepthNearest, true>(
+          t, q, node, INFINITY, L, lds_n, lds_d, ovf_n, ovf_d, sp, nl, reads, &pend);
       if (node < 0) node = knn_pop<B>(L.kth(), lds_n, lds_d, ovf_n, ovf_d, sp, nl);
       if (node < 0) {
         done = true;
         break;
       }
     }
+    pend.flush_all(L);
   }
   if (STATS) {
     stats[2 * qi] = visited;
