@@ -230,7 +230,7 @@ abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, 
  * frontier is split among the lanes, their pruning bound is shared, their
  * candidate lists are merged exactly).  Results do not depend on the value.
  * abx_set_nearest_budget sets the process-wide budget (<= 0: unlimited, i.e.
- * one lane per query throughout) and returns the previous one.  Default 16384.
+ * one lane per query throughout) and returns the previous one.  Default 24576.
  * A batch of m queries uses min(budget, max(512, m / 16)): small batches
  * leave the GPU idle and hand heavy queries to whole wavefronts sooner. */
 int64_t abx_set_nearest_budget(int64_t visits);

@@ -611,6 +611,8 @@ __global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
     bool active = true;
     int32_t node = -1;
     float bound = __uint_as_float(s_bound);
+    KnnPending pend;
+    pend.init();
     for (int64_t it = 0; it < 4 * t.n + 64; ++it) {
       // share the workgroup's bound: one LDS atomic per wave and step
       const float wm = wave_min(fminf(bound, L.kth()));
@@ -624,12 +626,13 @@ __global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
         if (node < 0) {
           active = false;
         } else {
-          node = knn_visit<KIND, FMT, K, S::kThreads, S::kWindow>(t, q, node, bound, L, lds_n,
-                                                                  lds_d, ovf_n, ovf_d, sp, nl,
-                                                                  reads);
+          node = knn_visit<KIND, FMT, K, S::kThreads, S::kWindow, true>(
+              t, q, node, bound, L, lds_n, lds_d, ovf_n, ovf_d, sp, nl, reads, &pend);
         }
       }
     }
+
+    pend.flush_all(L);
 
     // merge: each wave takes the k best of its 64 lists (k rounds of a
     // wave-wide minimum over the list fronts), then wave 0 the k best of the
