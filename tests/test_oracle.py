@@ -443,3 +443,26 @@ def test_nearest_degenerate_k_and_n(orc):
     assert off.tolist() == [0, 0, 0, 0]
     one = orc.build(pts[:1], orc.POINTS, 21)                  # n = 1: no internal node
     assert one["child_kind"].shape == (0, 2) and one["perm"].tolist() == [0]
+
+
+def test_paper_generators_geometry():
+    # section 3 data sets: a = p^(1/3), Omega = [-a, a]^3
+    p = 6_001
+    a = p ** (1 / 3)
+    fc = datagen.paper_filled_cube(p, 11).astype(np.float64)
+    assert fc.shape == (p, 3) and np.all(np.abs(fc) <= a)
+    hc = datagen.paper_hollow_cube(p, 12).astype(np.float64)
+    # point i on face i mod 6: axis (i mod 6) // 2, side -a for even faces
+    face = np.arange(p) % 6
+    on = hc[np.arange(p), face // 2]
+    np.testing.assert_allclose(on, np.where(face % 2 == 0, -a, a), rtol=1e-6)
+    assert np.all(np.abs(hc) <= a * (1 + 1e-6))
+    fs = datagen.paper_filled_sphere(p, 13).astype(np.float64)
+    assert np.all(np.linalg.norm(fs, axis=1) <= a * (1 + 1e-6))
+    hs = datagen.paper_hollow_sphere(p, 14).astype(np.float64)
+    np.testing.assert_allclose(np.linalg.norm(hs, axis=1), a, rtol=1e-5)
+    # the projection of a cube-uniform cloud is not uniform on the sphere:
+    # directions near the cube's corners are over-represented
+    d = np.abs(hs) / a
+    corner = np.mean(np.min(d, axis=1) > 0.5)
+    assert corner > 0.05
