@@ -215,7 +215,12 @@ abx_status abx_query_spatial_1p(const abx_bvh *bvh, const abx_predicates *preds,
  *   k' = min(k, n).  offsets[i] = i * k'; indices and distances are [m, k']
  *   in the caller's query order; distances are float32 Euclidean (point to
  *   box for box primitives).  No host synchronisation.  1 <= k <= 32 runs
- *   the register-resident kernels; larger k returns ABX_ERR_UNSUPPORTED. */
+ *   the register-resident kernels; larger k returns ABX_ERR_UNSUPPORTED.
+ *   Per axis the gap is max(lo - q, q - hi, 0) with IEEE max, which drops a
+ *   NaN operand: a NaN query coordinate contributes no gap on its axis (the
+ *   same for radius and box tests).  An infinite coordinate puts every
+ *   primitive at +inf: the row is the k' smallest indices (the tie rule),
+ *   after a walk of the whole tree. */
 abx_status abx_query_nearest_sizes(const abx_bvh *bvh, int64_t m, int32_t k,
                                    size_t *scratch_bytes /*host*/);
 abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, int64_t m,

@@ -358,3 +358,26 @@ def test_nearest_cooperative_boxes_and_ties(orc):
             check_nearest(orc, boxes, 1, q, 10, host(i), host(d))
     finally:
         abx.set_nearest_budget(old)
+
+
+def test_nearest_nan_and_infinite_queries(orc):
+    # a NaN coordinate adds no gap on its axis (IEEE max drops NaN; the
+    # oracle's comparisons do the same); an infinite one puts everything at
+    # +inf, where the tie rule picks the smallest indices
+    pts = datagen.uniform_cube(5_000, 81)
+    q = datagen.uniform_cube(300, 82)
+    q[7] = [np.nan, 0.5, 0.5]
+    q[8] = [np.inf, 0.5, 0.5]
+    q[9] = [-np.inf, np.inf, 0.5]
+    for fmt in ("fp32", "q16"):
+        t = abx.bvh_build(dev(pts), node_format=fmt)
+        _, ki, kd = abx.query_nearest(t, dev(q), 6)
+        ki, kd = host(ki), host(kd)
+        check_nearest(orc, pts, 0, q, 6, ki, kd, rows=[0, 7, 100])
+        for r in (8, 9):
+            assert ki[r].tolist() == list(range(6)) and np.all(np.isinf(kd[r]))
+        off, idx = abx.query_spatial(t, dev(q), radius=0.05)
+        check_spatial(orc, pts, 0, q, orc.WITHIN, host(off), host(idx), radius=0.05,
+                      rows=[0, 7, 8, 9])
+        cnt = np.diff(host(off))
+        assert cnt[7] > 0 and cnt[8] == 0 and cnt[9] == 0
