@@ -214,8 +214,10 @@ abx_status abx_query_spatial_1p(const abx_bvh *bvh, const abx_predicates *preds,
  *   smaller index); missing results are purged, so every row has length
  *   k' = min(k, n).  offsets[i] = i * k'; indices and distances are [m, k']
  *   in the caller's query order; distances are float32 Euclidean (point to
- *   box for box primitives).  No host synchronisation.  1 <= k <= 32 runs
- *   the register-resident kernels; larger k returns ABX_ERR_UNSUPPORTED.
+ *   box for box primitives).  No host synchronisation.  1 <= k <= 32 keeps
+ *   the candidates in registers (one lane per query, heavy queries handed to
+ *   whole workgroups); 33 <= k <= 128 keeps them in per-lane LDS max-heaps
+ *   (one lane per query throughout); larger k returns ABX_ERR_UNSUPPORTED.
  *   Per axis the gap is max(lo - q, q - hi, 0) with IEEE max, which drops a
  *   NaN operand: a NaN query coordinate contributes no gap on its axis (the
  *   same for radius and box tests).  An infinite coordinate puts every
@@ -385,7 +387,7 @@ typedef struct {
   const float *queries;    /* HOST [m,3]; read while the request runs         */
   int64_t m;
   float radius;            /* radius requests                                */
-  int32_t k;               /* nearest requests, 0..32                        */
+  int32_t k;               /* nearest requests, 0..128                       */
   double t_arrival;        /* caller's arrival time (abx_server_now clock)   */
 } abx_request;
 

@@ -67,6 +67,7 @@ std::vector<Pending> g_pending;
 std::map<std::string, std::pair<double, int64_t>> g_acc;
 
 constexpr int64_t kMaxCount = INT32_MAX;
+constexpr int64_t kMaxNearestK = 128;  // register lists up to 32, LDS heaps up to 128
 
 __global__ void k_row_offsets(int32_t *off, int64_t m, int32_t k) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -621,7 +622,7 @@ static abx_status nearest_common(const abx_bvh *bvh, const float *points, int64_
     return ABX_ERR_INVALID_ARG;
   const int64_t kk = k < bvh->n ? k : bvh->n;
   if (m * kk >= kMaxCount) return ABX_ERR_OVERFLOW;
-  if (kk > 32) return ABX_ERR_UNSUPPORTED;
+  if (kk > kMaxNearestK) return ABX_ERR_UNSUPPORTED;
   if (!stats && (!offsets || (m * kk > 0 && (!indices || !distances)))) return ABX_ERR_INVALID_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char *sc = static_cast<char *>(scratch);

@@ -490,7 +490,7 @@ abx_status abx_server_submit(abx_server *S, const abx_request *r, uint64_t *tick
   if (!S || !r || !ticket || r->m < 0 || (r->m > 0 && !r->queries && !S->cfg.simulate))
     return ABX_ERR_INVALID_ARG;
   if (r->kind != ABX_REQ_RADIUS && r->kind != ABX_REQ_NEAREST) return ABX_ERR_INVALID_ARG;
-  if (r->kind == ABX_REQ_NEAREST && (r->k < 0 || r->k > 32)) return ABX_ERR_INVALID_ARG;
+  if (r->kind == ABX_REQ_NEAREST && (r->k < 0 || r->k > 128)) return ABX_ERR_INVALID_ARG;
   if (r->m >= INT32_MAX) return ABX_ERR_OVERFLOW;
   Req *q = new (std::nothrow) Req;
   if (!q) return ABX_ERR_INVALID_ARG;

@@ -148,6 +148,154 @@ __attribute__((amdgpu_waves_per_eu(nearest_waves_per_eu(K)))) void k_nearest(Tre
       (ABX_LDS float *)(s_dist) + threadIdx.x, indices, dist, stats, budget, heavy);
 }
 
+// ------------------------------------------------------------ large k
+// k = 33..128: each lane keeps its candidates in an LDS max-heap (root = the
+// current k-th candidate; the heap is the paper's bounded priority list,
+// section 2.2), one wavefront per workgroup, entry e of lane l at e * 64 + l
+// so that a wavefront's accesses fall in distinct banks.  The walk is the
+// one of pass 1 (child with the nearer box centre first, strict pruning by
+// the root once the heap is full) with no visit budget.  At the end a heap
+// sort leaves the row ascending in place.
+constexpr int kHeapLanes = kWave;
+
+__device__ __forceinline__ void heap_push(ABX_LDS int64_t *h, int &size, int64_t x) {
+  int i = size++;
+  while (i > 0) {
+    const int p = (i - 1) >> 1;
+    const int64_t vp = h[p * kHeapLanes];
+    if (vp >= x) break;
+    h[i * kHeapLanes] = vp;
+    i = p;
+  }
+  h[i * kHeapLanes] = x;
+}
+
+// x replaces the root of heap [0, size) and sinks to its place
+__device__ __forceinline__ void heap_sink(ABX_LDS int64_t *h, int size, int64_t x) {
+  int i = 0;
+  for (;;) {
+    int c = 2 * i + 1;
+    if (c >= size) break;
+    int64_t vc = h[c * kHeapLanes];
+    if (c + 1 < size) {
+      const int64_t v2 = h[(c + 1) * kHeapLanes];
+      if (v2 > vc) {
+        ++c;
+        vc = v2;
+      }
+    }
+    if (vc <= x) break;
+    h[i * kHeapLanes] = vc;
+    i = c;
+  }
+  h[i * kHeapLanes] = x;
+}
+
+template <int KIND, int FMT, int KH, bool STATS>
+__global__ __launch_bounds__(kHeapLanes) void k_nearest_heap(TreeArgs t,
+                                                             const float *__restrict__ pts,
+                                                             int64_t m,
+                                                             const int32_t *__restrict__ order,
+                                                             int k, int32_t *__restrict__ indices,
+                                                             float *__restrict__ dist,
+                                                             int32_t *__restrict__ stats) {
+  __shared__ int64_t s_heap[KH * kHeapLanes];
+  __shared__ int32_t s_node[kLdsDepthNearest * kHeapLanes];
+  __shared__ float s_dist[kLdsDepthNearest * kHeapLanes];
+  const int64_t tq = xcd_tile(blockIdx.x, gridDim.x) * kHeapLanes + threadIdx.x;
+  if (tq >= m) return;
+  const int64_t qi = order ? order[tq] : tq;
+  const KnnQuery q{pts[3 * qi], pts[3 * qi + 1], pts[3 * qi + 2]};
+  ABX_LDS int64_t *h = (ABX_LDS int64_t *)(s_heap) + threadIdx.x;
+  ABX_LDS int32_t *lds_n = (ABX_LDS int32_t *)(s_node) + threadIdx.x;
+  ABX_LDS float *lds_d = (ABX_LDS float *)(s_dist) + threadIdx.x;
+  int size = 0;
+  int32_t visited = 0, reads = 0;
+  auto kth = [&]() { return size < k ? INFINITY : key_dist(h[0]); };
+  auto offer = [&](int64_t x) {
+    if (size < k) heap_push(h, size, x);
+    else if (x < h[0]) heap_sink(h, k, x);
+  };
+  // a leaf child whose node-stored box is at squared distance dbox
+  auto leaf = [&](int32_t idx, float dbox) {
+    if (!(dbox <= kth())) return;
+    if (exact_leaf_slots<KIND, FMT>()) {
+      offer(knn_key(dbox, idx));
+    } else {
+      ++reads;
+      float b[6];
+      load_leaf_box(t, idx, b);
+      const float d = box_dist2(b[0], b[1], b[2], b[3], b[4], b[5], q.x, q.y, q.z);
+      if (d <= kth()) offer(knn_key(d, idx));
+    }
+  };
+  if (t.n == 1) {
+    const float *b = t.scene;
+    leaf(0, box_dist2(b[0], b[1], b[2], b[3], b[4], b[5], q.x, q.y, q.z));
+  } else {
+    int32_t ovf_n[kMaxDepth];
+    float ovf_d[kMaxDepth];
+    int sp = 0, nl = 0;
+    int32_t node = t.root;
+    for (int64_t it = 0; it < 2 * t.n; ++it) {
+      if (STATS) ++visited;
+      Kids c;
+      load_kids<KIND, FMT>(t, node, c);
+      const float dl = box_dist2(c.l[0], c.l[1], c.l[2], c.l[3], c.l[4], c.l[5], q.x, q.y, q.z);
+      const float dr = box_dist2(c.r[0], c.r[1], c.r[2], c.r[3], c.r[4], c.r[5], q.x, q.y, q.z);
+      const bool ll = c.lref < 0, lr = c.rref < 0;
+      if (ll) leaf(~c.lref, dl);
+      if (lr) leaf(~c.rref, dr);
+      const float thr = kth();
+      const bool gl = !ll && dl <= thr, gr = !lr && dr <= thr;
+      node = -1;
+      if (gl && gr) {
+        float cl = 0.0f, cr = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float qa = a == 0 ? q.x : (a == 1 ? q.y : q.z);
+          const float ml = (c.l[a] - qa) - (qa - c.l[3 + a]);
+          const float mr = (c.r[a] - qa) - (qa - c.r[3 + a]);
+          cl = __fmaf_rn(ml, ml, cl);
+          cr = __fmaf_rn(mr, mr, cr);
+        }
+        const bool left_first = cl <= cr;
+        if (sp < kMaxDepth)
+          stack_push2<kLdsDepthNearest, kHeapLanes>(lds_n, lds_d, ovf_n, ovf_d, sp, nl,
+                                                    left_first ? c.rref : c.lref,
+                                                    left_first ? dr : dl);
+        node = left_first ? c.lref : c.rref;
+      } else if (gl) {
+        node = c.lref;
+      } else if (gr) {
+        node = c.rref;
+      }
+      if (node < 0) node = knn_pop<kHeapLanes>(kth(), lds_n, lds_d, ovf_n, ovf_d, sp, nl);
+      if (node < 0) break;
+    }
+  }
+  if (STATS) {
+    stats[2 * qi] = visited;
+    stats[2 * qi + 1] = reads;
+    return;
+  }
+  // heap sort: the largest goes to the back, the rest sinks again
+  for (int e = size - 1; e > 0; --e) {
+    const int64_t top = h[0];
+    const int64_t last = h[e * kHeapLanes];
+    h[e * kHeapLanes] = top;
+    heap_sink(h, e, last);
+  }
+  int32_t *oi = indices + qi * k;
+  float *od = dist + qi * k;
+  for (int j = 0; j < size; ++j) {
+    const int64_t x = h[j * kHeapLanes];
+    oi[j] = key_index(x);
+    od[j] = sqrtf(key_dist(x));
+  }
+}
+
+
 // ------------------------------------------------------------ query codes
 // 30-bit Morton code of each query's centroid against the tree's scene box
 // (clamped), for the query ordering of section 2.2.
@@ -351,6 +499,25 @@ abx_status nearest_k(const abx_bvh *b, const float *pts, int64_t m, const int32_
 }
 
 template <int KIND, int FMT>
+abx_status nearest_heap(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order, int k,
+                        int32_t *idx, float *dist, int32_t *stats, hipStream_t s) {
+  const TreeArgs t = tree_args(b);
+  const unsigned g = grid_for(m, kHeapLanes);
+#define ABX_HEAP(KH)                                                                          \
+  return launch(stats ? "nearest_stats" : "nearest", s, [&] {                                \
+    if (stats)                                                                                \
+      k_nearest_heap<KIND, FMT, KH, true><<<g, kHeapLanes, 0, s>>>(t, pts, m, order, k, idx,   \
+                                                                  dist, stats);               \
+    else                                                                                      \
+      k_nearest_heap<KIND, FMT, KH, false><<<g, kHeapLanes, 0, s>>>(t, pts, m, order, k, idx,  \
+                                                                   dist, stats);              \
+  })
+  if (k <= 64) ABX_HEAP(64);
+  ABX_HEAP(kMaxHeapK);
+#undef ABX_HEAP
+}
+
+template <int KIND, int FMT>
 abx_status nearest_fmt(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order, int k,
                        int32_t *idx, float *dist, int32_t *stats, const NearestScratch &ns,
                        hipStream_t s) {
@@ -375,7 +542,17 @@ abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const i
                           int k, int32_t *idx, float *dist, int32_t *stats, int32_t *heavy_q,
                           float *heavy_bound, uint32_t *counters, int64_t budget, hipStream_t s) {
   if (m == 0 || k == 0) return ABX_OK;
-  if (k > 32) return ABX_ERR_UNSUPPORTED;
+  if (k > kMaxHeapK) return ABX_ERR_UNSUPPORTED;
+  if (k > 32) {
+    if (b->kind == ABX_PRIM_POINTS) {
+      if (b->format == ABX_NODES_FP32)
+        return nearest_heap<ABX_PRIM_POINTS, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, s);
+      return nearest_heap<ABX_PRIM_POINTS, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, s);
+    }
+    if (b->format == ABX_NODES_FP32)
+      return nearest_heap<ABX_PRIM_BOXES, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, s);
+    return nearest_heap<ABX_PRIM_BOXES, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, s);
+  }
   const NearestScratch ns{heavy_q, heavy_bound, counters, effective_budget(budget, m)};
   if (b->kind == ABX_PRIM_POINTS) {
     if (b->format == ABX_NODES_FP32)

@@ -13,6 +13,7 @@ constexpr int kTravBlock = 256;
 constexpr int kMaxDepth = 128;
 constexpr int kLdsDepthSpatial = 16;
 constexpr int kLdsDepthNearest = 8;
+constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 33..128)
 
 // Occupancy target of the one-lane nearest pass (waves per SIMD).  Six beat
 // eight at k = 10 on the C3 shell (fewer walks competing for L2, no spills);

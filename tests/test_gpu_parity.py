@@ -381,3 +381,36 @@ def test_nearest_nan_and_infinite_queries(orc):
                       rows=[0, 7, 8, 9])
         cnt = np.diff(host(off))
         assert cnt[7] > 0 and cnt[8] == 0 and cnt[9] == 0
+
+
+@pytest.mark.parametrize("k", [33, 64, 100, 128])
+def test_nearest_large_k_heaps(orc, k):
+    # 33 <= k <= 128: candidates in per-lane LDS max-heaps
+    pts = datagen.clusters(20_000, 91)
+    q = datagen.uniform_cube(2_001, 92)
+    boxes = datagen.boxes_around(pts, 93, 0.003)
+    for kind, prims in ((0, pts), (1, boxes)):
+        for fmt in ("fp32", "q16"):
+            t = abx.bvh_build(dev(prims), kind=kind, node_format=fmt)
+            off, ki, kd = abx.query_nearest(t, dev(q), k)
+            assert host(off)[-1] == 2_001 * k
+            check_nearest(orc, prims, kind, q, k, host(ki), host(kd),
+                          rows=np.arange(0, 2_001, 23))
+            st = host(abx.query_nearest_stats(t, dev(q), k))
+            assert np.all(st[:, 0] >= 1)
+
+
+def test_nearest_large_k_edges(orc):
+    pts = datagen.uniform_cube(50, 94)
+    q = datagen.uniform_cube(70, 95)
+    t = abx.bvh_build(dev(pts), node_format="q16")
+    _, ki, kd = abx.query_nearest(t, dev(q), 100)          # k > n: rows of n
+    assert host(ki).shape == (70, 50)
+    check_nearest(orc, pts, 0, q, 100, host(ki), host(kd))
+    one = abx.bvh_build(dev(np.array([[0.5, 0.5, 0.5]], np.float32)))
+    _, ki, kd = abx.query_nearest(one, dev(q), 64)
+    assert host(ki).shape == (70, 1) and np.all(host(ki) == 0)
+    big = abx.bvh_build(dev(datagen.uniform_cube(500, 96)))
+    with pytest.raises(abx.AbxError) as e:
+        abx.query_nearest(big, dev(q), 129)
+    assert e.value.status == abx.ERR_UNSUPPORTED

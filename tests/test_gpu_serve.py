@@ -94,3 +94,20 @@ def test_serving_capacity_error_does_not_block():
     assert s.wait(b)["status"] == abx.ERR_CAPACITY
     assert s.wait(c)["status"] == abx.OK
     s.close()
+
+
+def test_serving_large_k_equals_direct_query(orc):
+    pts = datagen.uniform_cube(20_000, 15)
+    q = datagen.uniform_cube(777, 16)
+    tree = abx.bvh_build(torch.from_numpy(pts).cuda(), node_format="q16")
+    _, di, dd = abx.query_nearest(tree, torch.from_numpy(q).cuda(), 100)
+    s = abx.Server(slots=2, budget_bytes=64 << 20, host_bytes=64 << 20)
+    tid = s.add_tree(tree)
+    tk = s.submit(tid, abx.REQ_NEAREST, q, k=100)
+    r = s.wait(tk)
+    s.close()
+    assert r["status"] == abx.OK
+    assert np.array_equal(r["indices"].reshape(777, 100), di.cpu().numpy())
+    assert np.array_equal(r["distances"].reshape(777, 100), dd.cpu().numpy())
+    check_nearest(orc, pts, 0, q, 100, r["indices"].reshape(777, 100),
+                  r["distances"].reshape(777, 100), rows=np.arange(0, 777, 31))

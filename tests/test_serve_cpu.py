@@ -91,5 +91,5 @@ def test_submit_validation():
     with pytest.raises(abx.AbxError):
         s.submit(5, abx.REQ_NEAREST, np.zeros((3, 3), np.float32), k=2)   # unknown tree
     with pytest.raises(abx.AbxError):
-        s.submit(0, abx.REQ_NEAREST, np.zeros((3, 3), np.float32), k=33)  # k > 32
+        s.submit(0, abx.REQ_NEAREST, np.zeros((3, 3), np.float32), k=129)  # k > 128
     s.close()
