@@ -65,18 +65,51 @@ __global__ __launch_bounds__(kBuildBlock) void k_scene_partial(const float *__re
 // One thread per axis (plus one for the flag): final reduction and the Q16
 // grid.  The grid step s is the smallest float with
 // fmaf(65535, s, lo) >= hi, so the top code covers the scene box.
-__global__ void k_scene_final(const float *__restrict__ partial, int blocks,
-                              TreeHeader *__restrict__ hdr) {
+constexpr int kSceneFinalThreads = 256;
+
+__global__ __launch_bounds__(kSceneFinalThreads) void k_scene_final(const float *__restrict__ partial,
+                                                                    int blocks,
+                                                                    TreeHeader *__restrict__ hdr) {
+  // min / max / or over the partials (exact in any order), then the header
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;
+  for (int b = threadIdx.x; b < blocks; b += kSceneFinalThreads) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], partial[b * 8 + a]);
+      hi[a] = fmaxf(hi[a], partial[b * 8 + 3 + a]);
+    }
+    bad |= partial[b * 8 + 6] != 0.0f;
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], __shfl_down(lo[a], o, kWave));
+      hi[a] = fmaxf(hi[a], __shfl_down(hi[a], o, kWave));
+    }
+    bad |= __shfl_down(bad, o, kWave);
+  }
+  __shared__ float s[kSceneFinalThreads / kWave][7];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) {
+    for (int a = 0; a < 3; ++a) {
+      s[wave][a] = lo[a];
+      s[wave][3 + a] = hi[a];
+    }
+    s[wave][6] = (float)bad;
+  }
+  __syncthreads();
   const int a = threadIdx.x;
   if (a < 3) {
-    float lo = INFINITY, hi = -INFINITY;
-    for (int b = 0; b < blocks; ++b) {
-      lo = fminf(lo, partial[b * 8 + a]);
-      hi = fmaxf(hi, partial[b * 8 + 3 + a]);
+    float l = s[0][a], h = s[0][3 + a];
+    for (int w = 1; w < kSceneFinalThreads / kWave; ++w) {
+      l = fminf(l, s[w][a]);
+      h = fmaxf(h, s[w][3 + a]);
     }
-    hdr->scene[a] = lo;
-    hdr->scene[3 + a] = hi;
-    const float ext = hi - lo;
+    hdr->scene[a] = l;
+    hdr->scene[3 + a] = h;
+    const float ext = h - l;
     hdr->inv_ext[a] = ext > 0.0f ? 1.0f / ext : 0.0f;
     float sc = 0.0f;
     int overflow = 0;
@@ -85,16 +118,16 @@ __global__ void k_scene_final(const float *__restrict__ partial, int blocks,
         overflow = 1;
       } else {
         sc = ext / (float)kQ16Max;
-        while (__fmaf_rn((float)kQ16Max, sc, lo) < hi) sc = nextafterf(sc, INFINITY);
+        while (__fmaf_rn((float)kQ16Max, sc, l) < h) sc = nextafterf(sc, INFINITY);
       }
     }
-    hdr->q_origin[a] = lo;
+    hdr->q_origin[a] = l;
     hdr->q_scale[a] = sc;
     if (overflow) atomicOr(&hdr->bad, 2);
   } else if (a == 3) {
-    int bad = 0;
-    for (int b = 0; b < blocks; ++b) bad |= partial[b * 8 + 6] != 0.0f;
-    if (bad) atomicOr(&hdr->bad, 1);
+    int any = 0;
+    for (int w = 0; w < kSceneFinalThreads / kWave; ++w) any |= s[w][6] != 0.0f;
+    if (any) atomicOr(&hdr->bad, 1);
     hdr->height = 0;
   }
 }
@@ -287,10 +320,15 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_local(
     int32_t pp = parent_leaf[p];
     // the parent's reference to this leaf names the primitive itself
     reinterpret_cast<int32_t *>(nodes + (pp >> 1))[12 + (pp & 1)] = ~orig;
+    int64_t j = other_end[pp >> 1];
     for (int step = 0; step < kRefitMaxSteps; ++step) {
       const int32_t parent = pp >> 1, side = pp & 1;
+      // The climb is a chain of dependent reads.  The hierarchy arrays are
+      // read-only here, so the next parent is fetched before this level's
+      // hand-off and the next range end while the sibling's box is read:
+      // one exposed memory latency per level instead of three.
+      const int32_t up = parent_int[parent];
       store_child(nodes + parent, side, b, h);
-      const int64_t j = other_end[parent];
       const int64_t f = parent < j ? parent : j, l = parent < j ? j : parent;
       if (f < c0 || l >= c0 + kRefitChunk) {
         const uint32_t e = atomicAdd(frontier_count, 1u);
@@ -304,6 +342,7 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_local(
       float sb[6];
       int sh;
       load_child(nodes + parent, side ^ 1, sb, sh);
+      const int64_t jn = parent != 0 ? other_end[up >> 1] : 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         b[a] = fminf(b[a], sb[a]);
@@ -314,7 +353,8 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_local(
         hdr->height = h;
         break;
       }
-      pp = parent_int[parent];
+      pp = up;
+      j = jn;
       if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
     }
   }
@@ -337,6 +377,7 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_top(const int32_t *__re
     int h;
     load_child(nodes + parent, side, b, h);
     for (int step = 0; step < kRefitMaxSteps; ++step) {
+      const int32_t up = parent_int[parent];  // read-only: overlaps the hand-off
       const uint32_t old = __hip_atomic_fetch_add(flags + parent, 1u, __ATOMIC_ACQ_REL,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
       if (old == 0) break;
@@ -353,7 +394,7 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_top(const int32_t *__re
         hdr->height = h;
         break;
       }
-      pp = parent_int[parent];
+      pp = up;
       parent = pp >> 1;
       side = pp & 1;
       store_child(nodes + parent, side, b, h);
@@ -513,19 +554,28 @@ size_t refit_frontier_cap(int64_t n) {
 }
 
 // ------------------------------------------------------------ Q16 nodes
-__device__ __forceinline__ uint32_t q_lo(float x, float o, float s) {
+// The 16-bit code of a box's lower (upper) face: the largest (smallest) q
+// whose dequantised value fmaf(q, s, o) is <= x (>= x), so the decoded box
+// contains the exact one and is the tightest such box.  dequantisation is
+// monotone in q, so the estimate from inv = 1/s (any nearby start) is moved
+// to that q by the two loops; they take a step or two at most.
+__device__ __forceinline__ uint32_t q_clamp(double e) {
+  return e <= 0.0 ? 0u : (e >= (double)kQ16Max ? (uint32_t)kQ16Max : (uint32_t)e);
+}
+
+__device__ __forceinline__ uint32_t q_lo(float x, float o, float s, double inv) {
   if (s == 0.0f) return 0;
-  double e = floor(((double)x - (double)o) / (double)s);
-  uint32_t q = e <= 0.0 ? 0u : (e >= (double)kQ16Max ? (uint32_t)kQ16Max : (uint32_t)e);
+  uint32_t q = q_clamp(floor(((double)x - (double)o) * inv));
   while (q > 0 && deq(q, s, o) > x) --q;
+  while (q < (uint32_t)kQ16Max && deq(q + 1, s, o) <= x) ++q;
   return q;
 }
 
-__device__ __forceinline__ uint32_t q_hi(float x, float o, float s) {
+__device__ __forceinline__ uint32_t q_hi(float x, float o, float s, double inv) {
   if (s == 0.0f) return 0;
-  double e = ceil(((double)x - (double)o) / (double)s);
-  uint32_t q = e <= 0.0 ? 0u : (e >= (double)kQ16Max ? (uint32_t)kQ16Max : (uint32_t)e);
+  uint32_t q = q_clamp(ceil(((double)x - (double)o) * inv));
   while (q < (uint32_t)kQ16Max && deq(q, s, o) < x) ++q;
+  while (q > 0 && deq(q - 1, s, o) >= x) --q;
   return q;
 }
 
@@ -542,6 +592,14 @@ __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restr
   if (i >= ni) return;
   const float *f = reinterpret_cast<const float *>(src + i);
   const int4 d = src[i].d;
+  float o[3], sc[3];
+  double inv[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    o[a] = hdr->q_origin[a];
+    sc[a] = hdr->q_scale[a];
+    inv[a] = sc[a] != 0.0f ? 1.0 / (double)sc[a] : 0.0;
+  }
   uint32_t w[6];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -553,9 +611,8 @@ __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restr
       uint32_t q[6];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const float o = hdr->q_origin[a], sc = hdr->q_scale[a];
-        q[a] = q_lo(f[6 * c + a], o, sc);
-        q[3 + a] = q_hi(f[6 * c + 3 + a], o, sc);
+        q[a] = q_lo(f[6 * c + a], o[a], sc[a], inv[a]);
+        q[3 + a] = q_hi(f[6 * c + 3 + a], o[a], sc[a], inv[a]);
       }
 #pragma unroll
       for (int h = 0; h < 3; ++h) w[3 * c + h] = q[2 * h] | (q[2 * h + 1] << 16);
@@ -579,7 +636,7 @@ abx_status launch_scene(int kind, const float *prims, int64_t n, float *partial,
     ABX_TRY(launch("scene_partial", s, [&] {
       k_scene_partial<ABX_PRIM_BOXES><<<blocks, kBuildBlock, 0, s>>>(prims, n, partial);
     }));
-  return launch("scene_final", s, [&] { k_scene_final<<<1, 64, 0, s>>>(partial, blocks, hdr); });
+  return launch("scene_final", s, [&] { k_scene_final<<<1, kSceneFinalThreads, 0, s>>>(partial, blocks, hdr); });
 }
 
 int scene_blocks(int64_t n) {

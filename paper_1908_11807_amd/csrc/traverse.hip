@@ -191,15 +191,17 @@ __device__ __forceinline__ void heap_sink(ABX_LDS int64_t *h, int size, int64_t 
   h[i * kHeapLanes] = x;
 }
 
-template <int KIND, int FMT, int KH, bool STATS>
-__global__ __launch_bounds__(kHeapLanes) void k_nearest_heap(TreeArgs t,
+// The heap takes 8k bytes of LDS per lane (dynamic, sized to k), which is
+// what bounds residency: registers are capped to match (4 waves per SIMD).
+template <int KIND, int FMT, bool STATS>
+__global__ __launch_bounds__(kHeapLanes) __attribute__((amdgpu_waves_per_eu(4))) void k_nearest_heap(TreeArgs t,
                                                              const float *__restrict__ pts,
                                                              int64_t m,
                                                              const int32_t *__restrict__ order,
                                                              int k, int32_t *__restrict__ indices,
                                                              float *__restrict__ dist,
                                                              int32_t *__restrict__ stats) {
-  __shared__ int64_t s_heap[KH * kHeapLanes];
+  extern __shared__ int64_t s_heap[];  // k keys per lane, lane-interleaved
   __shared__ int32_t s_node[kLdsDepthNearest * kHeapLanes];
   __shared__ float s_dist[kLdsDepthNearest * kHeapLanes];
   const int64_t tq = xcd_tile(blockIdx.x, gridDim.x) * kHeapLanes + threadIdx.x;
@@ -498,23 +500,29 @@ abx_status nearest_k(const abx_bvh *b, const float *pts, int64_t m, const int32_
   });
 }
 
+template <int KIND, int FMT, bool STATS>
+abx_status launch_heap(const TreeArgs &t, const float *pts, int64_t m, const int32_t *order, int k,
+                       int32_t *idx, float *dist, int32_t *stats, hipStream_t s) {
+  const size_t heap_bytes = (size_t)k * kHeapLanes * sizeof(int64_t);
+  // above 64 KB a kernel must be allowed the larger dynamic LDS explicitly
+  // (on the current device; cheap, so done at every launch)
+  const hipError_t allowed = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(&k_nearest_heap<KIND, FMT, STATS>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)heap_bytes);
+  if (allowed != hipSuccess) return hip_fail(allowed);
+  const unsigned g = grid_for(m, kHeapLanes);
+  return launch(STATS ? "nearest_stats" : "nearest", s, [&] {
+    k_nearest_heap<KIND, FMT, STATS><<<g, kHeapLanes, heap_bytes, s>>>(t, pts, m, order, k, idx, dist,
+                                                                      stats);
+  });
+}
+
 template <int KIND, int FMT>
 abx_status nearest_heap(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order, int k,
                         int32_t *idx, float *dist, int32_t *stats, hipStream_t s) {
   const TreeArgs t = tree_args(b);
-  const unsigned g = grid_for(m, kHeapLanes);
-#define ABX_HEAP(KH)                                                                          \
-  return launch(stats ? "nearest_stats" : "nearest", s, [&] {                                \
-    if (stats)                                                                                \
-      k_nearest_heap<KIND, FMT, KH, true><<<g, kHeapLanes, 0, s>>>(t, pts, m, order, k, idx,   \
-                                                                  dist, stats);               \
-    else                                                                                      \
-      k_nearest_heap<KIND, FMT, KH, false><<<g, kHeapLanes, 0, s>>>(t, pts, m, order, k, idx,  \
-                                                                   dist, stats);              \
-  })
-  if (k <= 64) ABX_HEAP(64);
-  ABX_HEAP(kMaxHeapK);
-#undef ABX_HEAP
+  if (stats) return launch_heap<KIND, FMT, true>(t, pts, m, order, k, idx, dist, stats, s);
+  return launch_heap<KIND, FMT, false>(t, pts, m, order, k, idx, dist, stats, s);
 }
 
 template <int KIND, int FMT>
