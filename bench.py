@@ -252,20 +252,6 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def forest_inputs(n_trees, seed=401):
-    """256 trees, sizes log-uniform in [1e3, 1e6]; even ids uniform cube, odd
-    ids Gaussian clusters; each tree's queries from its own distribution."""
-    from paper_1908_11807_amd import datagen
-    sizes = datagen.forest_sizes(n_trees, seed)
-    pts, qs = [], []
-    for t, n in enumerate(sizes):
-        p, q = datagen.forest_tree(t, int(n), seed)
-        pts.append(p)
-        qs.append(q)
-    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    return np.concatenate(pts), off, np.concatenate(qs), off.copy()
-
-
 def bench_paper(args):
     """The paper's two experimental cases (section 3, data sets) over m = n:
     filled (filled-sphere queries in a filled-cube cloud) and hollow
@@ -329,9 +315,9 @@ def bench_paper(args):
 
 def bench_forest(args):
     import torch
-    from paper_1908_11807_amd import abx
+    from paper_1908_11807_amd import abx, datagen
     k = 16
-    pts_np, off, q_np, qoff = forest_inputs(args.trees)
+    pts_np, off, q_np, qoff = datagen.forest_inputs(args.trees)
     N, M = int(off[-1]), int(qoff[-1])
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):

@@ -167,6 +167,21 @@ def forest_tree(t: int, size: int, base_seed: int = 401) -> tuple[np.ndarray, np
     return gen(size, base_seed + t), gen(size, base_seed + t + 100000)
 
 
+def forest_inputs(n_trees: int, seed: int = 401):
+    """The forest workload: ``n_trees`` trees with sizes log-uniform in
+    [1e3, 1e6]; even ids uniform cube, odd ids Gaussian clusters; each tree
+    has as many queries as points, from its own distribution.  Returns
+    (points, offsets, queries, query offsets), offsets int64 of length T+1."""
+    sizes = forest_sizes(n_trees, seed)
+    pts, qs = [], []
+    for t, n in enumerate(sizes):
+        p, q = forest_tree(t, int(n), seed)
+        pts.append(p)
+        qs.append(q)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return np.concatenate(pts), off, np.concatenate(qs), off.copy()
+
+
 def request_stream(n_req: int, seed: int, rate_hz: float, n_trees: int,
                    lo_exp: float = 0.0, hi_exp: float = 5.0,
                    kinds=("radius", 1, 8, 32)):
