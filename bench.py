@@ -80,6 +80,24 @@ def algorithmic_bytes(stats, node_b, leaf_b, per_query_fixed):
     return int(per_query_fixed * s.shape[0] + node_b * s[:, 0].sum() + leaf_b * s[:, 1].sum())
 
 
+def build_bytes_per_prim(node_format, morton_bits, kind_width=3):
+    """Algorithmic bytes of one build, per point primitive (Karras hierarchy,
+    two-phase refit, 8-bit radix digits)."""
+    keyb = 8 if morton_bits > 10 else 4          # 63- or 30-bit Morton keys
+    passes = 8 if morton_bits > 10 else 4        # 8-bit digits
+    w = 4 * kind_width                           # 12 B point (24 B box)
+    b = w                                        # scene box: read the primitives
+    b += w + keyb + 4                            # Morton: read, write key and index
+    b += keyb                                    # digit histograms: read the keys once
+    b += passes * 2 * (keyb + 4)                 # onesweep passes: read and write (key, index)
+    b += keyb + 8 + 8                            # hierarchy: keys, child refs, parent + range end
+    b += 4 + w + 4                               # refit, leaf: permutation, primitive, parent
+    b += 4 + 4 + 64 + 28                         # refit, node: parent, range end, node, sibling
+    if node_format == "q16":
+        b += 64 + 32                             # quantise: read FP32 node, write Q16 node
+    return b
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -156,7 +174,7 @@ def main():
     step_ms = phases.sum(axis=1)
     build_ms, rad_ms, knn_ms = np.median(phases, axis=0)
 
-    kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_top", "agglo",
+    kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_mid", "refit_top", "agglo",
                "agglo_top", "quantise",
                "scene_partial", "query_codes", "spatial_count", "spatial_fill", "scan_tiles", "nearest",
                "nearest_coop"]
@@ -200,6 +218,18 @@ def main():
         roof = dict(kernel=dom, bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=None, traffic=None)
 
+    # the other two phases against the same HBM peak (algorithmic bytes)
+    bpp = build_bytes_per_prim(args.nodes, args.morton_bits)
+    rad_bytes = alg["spatial_count"] + alg["spatial_fill"]
+    phase_rooflines = {
+        "build": dict(bytes_per_prim=bpp, achieved=round(bpp * n / (build_ms * 1e-3) / 1e9, 1),
+                      peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(bpp * n / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
+        "radius_2p": dict(bytes=rad_bytes, achieved=round(rad_bytes / (rad_ms * 1e-3) / 1e9, 1),
+                          peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(rad_bytes / (rad_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
+    }
+
     out = {
         "metric": "queries/s (kNN k=10, radius) + BVH build Mprims/s at 1e7 pts; p99 batch latency",
         "value": round(2 * m / (ms_step * 1e-3), 1),
@@ -220,6 +250,7 @@ def main():
         "step_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                             "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "radius_results": hits,
+        "phase_rooflines": phase_rooflines,
         "tree_height": t.height,
         "kernels": {kn: {kk: round(v, 4) for kk, v in d.items()} for kn, d in ktimes.items()},
         "roofline": roof,

@@ -280,10 +280,11 @@ __device__ __forceinline__ void load_child(const NodeF32 *node, int side, float 
 // is read back from the node in global memory, ordered by the counter's
 // acquire-release).  A thread that reaches a node whose range crosses the
 // chunk boundary stops there and appends (node, side) to the frontier list.
-// Phase 2 (one workgroup, after the kernel boundary has made phase 1's
-// stores visible): climbs from every frontier entry through the crossing
-// nodes, again with workgroup-scope synchronisation.  No step needs
-// agent-scope fences (which would write back and invalidate the XCDs' L2s).
+// Phase 2 (one workgroup per 64 chunks) climbs the crossing nodes inside its
+// 64 chunks; phase 3 (one workgroup) the few that cross those groups.  Each
+// phase starts after a kernel boundary has made the previous one's stores
+// visible and synchronises at workgroup scope.  No step needs agent-scope
+// fences (which would write back and invalidate the XCDs' L2s).
 constexpr int kRefitThreads = 1024;
 constexpr int kRefitPerThread = 8;
 constexpr int kRefitChunk = kRefitThreads * kRefitPerThread;
@@ -360,7 +361,104 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_local(
   }
 }
 
-// Phase 2: one workgroup climbs the nodes that cross chunk boundaries.
+// Phase 2: one workgroup per super-chunk of kMidChunks chunks climbs the
+// chunk-crossing nodes whose leaf range lies inside its super-chunk.  All
+// arrivals at such a node come from that workgroup (from its own entries or
+// its own climbs), so workgroup-scope counters in global memory suffice.  A
+// climb that reaches a node crossing a super-chunk boundary stores its box
+// there and hands (node, side) to the last phase.  Entries are routed by the
+// super-chunk holding the first leaf of the node's range; each workgroup
+// reads the whole list in unrolled batches, so the reads overlap.
+constexpr int kMidChunks = 64;
+constexpr int64_t kMidLeaves = (int64_t)kRefitChunk * kMidChunks;
+// A crossing node inside a super-chunk is an ancestor of the split at one of
+// its kMidChunks - 1 inner chunk boundaries, so there are at most
+// (kMidChunks - 1) * (tree height, < 96 for 63-bit keys augmented by 31-bit
+// positions) of them, each with at most two entries.
+constexpr int kMidListCap = 2 * kMidChunks * 96;
+
+__global__ __launch_bounds__(kRefitThreads) void k_refit_mid(
+    const int32_t *__restrict__ parent_int, const int32_t *__restrict__ other_end, NodeF32 *nodes,
+    uint32_t *flags, TreeHeader *hdr, const int32_t *__restrict__ fa,
+    const uint32_t *__restrict__ fa_count, int32_t *__restrict__ fb, uint32_t *__restrict__ fb_count,
+    uint32_t cap) {
+  __shared__ int32_t s_list[kMidListCap];
+  __shared__ uint32_t s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const uint32_t cnt = min(*fa_count, cap);
+  const int64_t s0 = (int64_t)blockIdx.x * kMidLeaves, s1 = s0 + kMidLeaves;
+  constexpr int kBatch = 8;
+  for (uint32_t e0 = threadIdx.x; e0 < cnt; e0 += kBatch * kRefitThreads) {
+    int32_t pp[kBatch], j[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const uint32_t e = e0 + (uint32_t)u * kRefitThreads;
+      pp[u] = e < cnt ? fa[e] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) j[u] = pp[u] >= 0 ? other_end[pp[u] >> 1] : 0;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (pp[u] < 0) continue;
+      const int64_t p = pp[u] >> 1;
+      const int64_t f = p < j[u] ? p : j[u], l = p < j[u] ? j[u] : p;
+      if (f < s0 || f >= s1) continue;  // another super-chunk's entry
+      if (l >= s1) {
+        const uint32_t e = atomicAdd(fb_count, 1u);
+        if (e < cap) fb[e] = pp[u];
+        else atomicOr(&hdr->bad, 4);
+      } else {
+        const uint32_t e = atomicAdd(&s_n, 1u);
+        if (e < (uint32_t)kMidListCap) s_list[e] = pp[u];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t own = min(s_n, (uint32_t)kMidListCap);
+  if (threadIdx.x == 0 && s_n > (uint32_t)kMidListCap) atomicOr(&hdr->bad, 4);
+  for (uint32_t e = threadIdx.x; e < own; e += kRefitThreads) {
+    int32_t pp = s_list[e];
+    int32_t parent = pp >> 1, side = pp & 1;
+    float b[6];
+    int h;
+    load_child(nodes + parent, side, b, h);
+    for (int step = 0; step < kRefitMaxSteps; ++step) {
+      const int32_t up = parent_int[parent];  // read-only: overlaps the hand-off
+      const uint32_t old = __hip_atomic_fetch_add(flags + parent, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      float sb[6];
+      int sh;
+      load_child(nodes + parent, side ^ 1, sb, sh);
+      const int64_t jn = parent != 0 ? other_end[up >> 1] : 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], sb[a]);
+        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+      }
+      h = (h > sh ? h : sh) + 1;
+      if (parent == 0) {
+        hdr->height = h;
+        break;
+      }
+      pp = up;
+      parent = pp >> 1;
+      side = pp & 1;
+      store_child(nodes + parent, side, b, h);
+      const int64_t f = parent < jn ? parent : jn, l = parent < jn ? jn : parent;
+      if (f < s0 || l >= s1) {
+        const uint32_t e2 = atomicAdd(fb_count, 1u);
+        if (e2 < cap) fb[e2] = pp;
+        else atomicOr(&hdr->bad, 4);
+        break;
+      }
+      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+}
+
+// Phase 3: one workgroup climbs the nodes that cross super-chunk boundaries.
 // The arrival counters are the global `flags` (cleared by the hierarchy
 // kernel); every hand-off is between threads of this one workgroup.
 __global__ __launch_bounds__(kRefitThreads) void k_refit_top(const int32_t *__restrict__ parent_int,
@@ -550,7 +648,7 @@ size_t agglo_frontier_cap(int64_t n) {
 // lies on the root path of some chunk boundary
 size_t refit_frontier_cap(int64_t n) {
   const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
-  return (size_t)(2 * 128 * chunks + 64);
+  return 2 * (size_t)(2 * 128 * chunks + 64);  // two lists: chunk and super-chunk crossings
 }
 
 // ------------------------------------------------------------ Q16 nodes
@@ -690,8 +788,8 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
                         uint32_t *frontier_count, hipStream_t s) {
   if (n == 0) return ABX_OK;
   const unsigned g = grid_for(n, kRefitChunk);
-  const uint32_t cap = (uint32_t)refit_frontier_cap(n);
-  ABX_TRY(fill_u32(frontier_count, 0, 1, s));
+  const uint32_t cap = (uint32_t)(refit_frontier_cap(n) / 2);  // per list
+  ABX_TRY(fill_u32(frontier_count, 0, 2, s));
 #define ABX_REFIT(KD, QQ)                                                                        \
   ABX_TRY(launch("refit", s, [&] {                                                              \
     k_refit_local<KD, QQ><<<g, kRefitThreads, 0, s>>>(prims, perm, n, parent_leaf, parent_int, \
@@ -707,9 +805,16 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
   }
 #undef ABX_REFIT
   if (n <= kRefitChunk) return ABX_OK;
+  int32_t *frontier2 = frontier + cap;
+  const unsigned g2 = (unsigned)((n + kMidLeaves - 1) / kMidLeaves);
+  ABX_TRY(launch("refit_mid", s, [&] {
+    k_refit_mid<<<g2, kRefitThreads, 0, s>>>(parent_int, other_end, nodes, flags, hdr, frontier,
+                                             frontier_count, frontier2, frontier_count + 1, cap);
+  }));
+  if (n <= kMidLeaves) return ABX_OK;
   return launch("refit_top", s, [&] {
-    k_refit_top<<<1, kRefitThreads, 0, s>>>(parent_int, nodes, flags, hdr, frontier,
-                                            frontier_count, cap);
+    k_refit_top<<<1, kRefitThreads, 0, s>>>(parent_int, nodes, flags, hdr, frontier2,
+                                            frontier_count + 1, cap);
   });
 }
 

@@ -114,6 +114,16 @@ def test_build_formats_and_kinds(orc, fmt, kind):
     _check_tree_vs_oracle(orc, prims, kind, 21, fmt)
 
 
+@pytest.mark.parametrize("kind,fmt", [(0, "fp32"), (1, "q16")])
+def test_build_all_refit_phases(orc, kind, fmt):
+    # 1.3e6 leaves: 159 chunks of 8192 in three groups of 64 (the last one
+    # ragged), so the in-chunk, in-group and cross-group refit phases all run
+    pts = datagen.shell(1_300_000, 77, 0.99, 1.01)
+    prims = pts if kind == 0 else datagen.boxes_around(pts, 78, 0.001)
+    t = _check_tree_vs_oracle(orc, prims, kind, 21, fmt)
+    assert t.height >= 2
+
+
 def test_build_duplicates_and_degenerate_axis(orc):
     rng = np.random.default_rng(1)
     pts = rng.integers(0, 4, size=(3000, 3)).astype(np.float32)   # heavy duplicates
