@@ -174,7 +174,7 @@ def main():
     step_ms = phases.sum(axis=1)
     build_ms, rad_ms, knn_ms = np.median(phases, axis=0)
 
-    kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_mid", "refit_top", "agglo",
+    kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_mid", "refit_top", "agglo", "agglo_mid",
                "agglo_top", "quantise",
                "scene_partial", "query_codes", "spatial_count", "spatial_fill", "scan_tiles", "nearest",
                "nearest_coop"]

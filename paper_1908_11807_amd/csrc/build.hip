@@ -641,7 +641,7 @@ __global__ __launch_bounds__(kRefitThreads) void k_agglo_top(const K *__restrict
 
 // at most two arrivals per split between chunks
 size_t agglo_frontier_cap(int64_t n) {
-  return (size_t)(2 * ((n + kRefitChunk - 1) / kRefitChunk) + 64);
+  return (size_t)(2 * ((n + kRefitChunk - 1) / kRefitChunk) + 64);  // per list (two lists)
 }
 
 // frontier entries: a crossing node has at most two, and every crossing node
@@ -831,6 +831,87 @@ abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, const TreeH
   });
 }
 
+// Middle pass of the agglomerative build (one workgroup per group of
+// kMidChunks chunks): climbs from the frontier entries whose split lies
+// strictly inside the group (both of its leaves in the group), through
+// splits inside the group only.  Every node it completes has all its splits
+// in the group, so every arrival it counts comes from this workgroup; a
+// split on or beyond the group's edge goes to the last pass's list
+// uncounted, as the chunk pass does at chunk edges.
+template <typename K>
+__global__ __launch_bounds__(kRefitThreads) void k_agglo_mid(const K *__restrict__ keys, int64_t n,
+                                                             NodeF32 *nodes, int32_t *range_lo,
+                                                             int32_t *range_hi, uint32_t *flags,
+                                                             TreeHeader *hdr,
+                                                             const int32_t *__restrict__ fa,
+                                                             const uint32_t *__restrict__ fa_count,
+                                                             int32_t *__restrict__ fb,
+                                                             uint32_t *__restrict__ fb_count,
+                                                             uint32_t cap) {
+  __shared__ int32_t s_list[kMidListCap];
+  __shared__ uint32_t s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const uint32_t cnt = min(*fa_count, cap);
+  const int64_t s0 = (int64_t)blockIdx.x * kMidLeaves, s1 = s0 + kMidLeaves;
+  const int64_t last = (s1 < n ? s1 : n) - 2;  // last split inside the group
+  for (uint32_t e = threadIdx.x; e < cnt; e += kRefitThreads) {
+    const int64_t p = fa[e];
+    if (p < s0 || p >= s1) continue;  // another group's entry
+    if (p > last) {
+      const uint32_t i = atomicAdd(fb_count, 1u);
+      if (i < cap) fb[i] = (int32_t)p;
+      else atomicOr(&hdr->bad, 4);
+    } else {
+      const uint32_t i = atomicAdd(&s_n, 1u);
+      if (i < (uint32_t)kMidListCap) s_list[i] = (int32_t)p;
+    }
+  }
+  __syncthreads();
+  const uint32_t own = min(s_n, (uint32_t)kMidListCap);
+  if (threadIdx.x == 0 && s_n > (uint32_t)kMidListCap) atomicOr(&hdr->bad, 4);
+  for (uint32_t e = threadIdx.x; e < own; e += kRefitThreads) {
+    int64_t p = s_list[e];
+    for (int step = 0; step < kRefitMaxSteps; ++step) {
+      const uint32_t old = __hip_atomic_fetch_add(flags + p, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      float b[6], sb[6];
+      int h, sh;
+      load_child(nodes + p, 0, b, h);
+      load_child(nodes + p, 1, sb, sh);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], sb[a]);
+        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+      }
+      h = (h > sh ? h : sh) + 1;
+      const int64_t l = range_lo[p], r = range_hi[p];
+      if (l == 0 && r == n - 1) {
+        hdr->root = (int32_t)p;
+        hdr->height = h;
+        break;
+      }
+      const bool left = l == 0 || (r != n - 1 && delta(keys, n, r, keys[r], r + 1) >
+                                                     delta(keys, n, l - 1, keys[l - 1], l));
+      const int64_t q = left ? r : l - 1;
+      const int side = left ? 0 : 1;
+      store_child(nodes + q, side, b, h);
+      reinterpret_cast<int32_t *>(nodes + q)[12 + side] = (int32_t)p;
+      if (left) range_lo[q] = (int32_t)l;
+      else range_hi[q] = (int32_t)r;
+      if (q < s0 || q > last) {
+        const uint32_t i = atomicAdd(fb_count, 1u);
+        if (i < cap) fb[i] = (int32_t)q;
+        else atomicOr(&hdr->bad, 4);
+        break;
+      }
+      p = q;
+      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+}
+
 abx_status launch_agglo(bool wide, int kind, bool q16, const void *keys, const float *prims,
                         const int32_t *perm, int64_t n, NodeF32 *nodes, int32_t *range_lo,
                         int32_t *range_hi, uint32_t *flags, TreeHeader *hdr, void *q16_leaves,
@@ -838,7 +919,7 @@ abx_status launch_agglo(bool wide, int kind, bool q16, const void *keys, const f
   if (n == 0) return ABX_OK;
   const unsigned g = grid_for(n, kRefitChunk);
   const uint32_t cap = (uint32_t)agglo_frontier_cap(n);
-  ABX_TRY(fill_u32(frontier_count, 0, 1, s));
+  ABX_TRY(fill_u32(frontier_count, 0, 2, s));
 #define ABX_AGG(KT, KD, QQ)                                                                       \
   ABX_TRY(launch("agglo", s, [&] {                                                               \
     k_agglo_local<KT, KD, QQ><<<g, kRefitThreads, 0, s>>>(static_cast<const KT *>(keys), prims,  \
@@ -862,16 +943,31 @@ abx_status launch_agglo(bool wide, int kind, bool q16, const void *keys, const f
 #undef ABX_AGG_KIND
 #undef ABX_AGG
   if (n <= kRefitChunk) return ABX_OK;
-  if (wide)
+  int32_t *frontier2 = frontier + cap;
+  const unsigned g2 = (unsigned)((n + kMidLeaves - 1) / kMidLeaves);
+  if (wide) {
+    const uint64_t *k64 = static_cast<const uint64_t *>(keys);
+    ABX_TRY(launch("agglo_mid", s, [&] {
+      k_agglo_mid<uint64_t><<<g2, kRefitThreads, 0, s>>>(k64, n, nodes, range_lo, range_hi, flags,
+                                                         hdr, frontier, frontier_count, frontier2,
+                                                         frontier_count + 1, cap);
+    }));
+    if (n <= kMidLeaves) return ABX_OK;
     return launch("agglo_top", s, [&] {
-      k_agglo_top<uint64_t><<<1, kRefitThreads, 0, s>>>(static_cast<const uint64_t *>(keys), n, nodes,
-                                                        range_lo, range_hi, flags, hdr, frontier,
-                                                        frontier_count, cap);
+      k_agglo_top<uint64_t><<<1, kRefitThreads, 0, s>>>(k64, n, nodes, range_lo, range_hi, flags,
+                                                        hdr, frontier2, frontier_count + 1, cap);
     });
+  }
+  const uint32_t *k32 = static_cast<const uint32_t *>(keys);
+  ABX_TRY(launch("agglo_mid", s, [&] {
+    k_agglo_mid<uint32_t><<<g2, kRefitThreads, 0, s>>>(k32, n, nodes, range_lo, range_hi, flags,
+                                                       hdr, frontier, frontier_count, frontier2,
+                                                       frontier_count + 1, cap);
+  }));
+  if (n <= kMidLeaves) return ABX_OK;
   return launch("agglo_top", s, [&] {
-    k_agglo_top<uint32_t><<<1, kRefitThreads, 0, s>>>(static_cast<const uint32_t *>(keys), n, nodes,
-                                                      range_lo, range_hi, flags, hdr, frontier,
-                                                      frontier_count, cap);
+    k_agglo_top<uint32_t><<<1, kRefitThreads, 0, s>>>(k32, n, nodes, range_lo, range_hi, flags, hdr,
+                                                      frontier2, frontier_count + 1, cap);
   });
 }
 

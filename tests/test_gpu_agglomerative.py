@@ -117,3 +117,34 @@ def test_shell_nearest_and_one_point():
     one = abx.bvh_build(dev(np.array([[0.25, 0.5, 0.75]], np.float32)), hierarchy="agglomerative")
     _, i1, d1 = abx.query_nearest(one, dev(np.array([[0.25, 0.5, 0.5]], np.float32)), 3)
     assert host(i1).tolist() == [[0]] and abs(float(host(d1)[0, 0]) - 0.25) < 1e-7
+
+
+def _sorted_rows(a):
+    a = np.ascontiguousarray(a)
+    return a[np.lexsort(a.T[::-1])]
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+def test_large_tree_all_build_phases(orc, fmt):
+    # 1.3e6 leaves: 159 chunks in three groups of 64 (the last ragged), so the
+    # chunk, group and top passes of both hierarchy builds all run.  The two
+    # builds make the same binary radix tree under different node numbering:
+    # the multisets of child boxes are equal, and so are query results.
+    n = 1_300_000
+    pts = datagen.shell(n, 79, 0.99, 1.01)
+    tk = abx.bvh_build(dev(pts), node_format=fmt)
+    ta = abx.bvh_build(dev(pts), node_format=fmt, hierarchy="agglomerative")
+    assert ta.layout.height == tk.layout.height
+    da, dk = decode_tree(ta), decode_tree(tk)
+    assert np.array_equal(da["perm"], dk["perm"])
+    keys = ("boxes_l", "boxes_r") if fmt == "fp32" else ("q_l", "q_r")
+    for d in (da, dk):
+        assert np.sum(d["child_kind"] == 0) == n   # every leaf referenced once
+    rows_a = _sorted_rows(np.concatenate([da[keys[0]], da[keys[1]]]))
+    rows_k = _sorted_rows(np.concatenate([dk[keys[0]], dk[keys[1]]]))
+    assert np.array_equal(rows_a, rows_k)
+    q = datagen.uniform_cube(100_000, 80, -1.0, 1.0)
+    _, ia, da_ = abx.query_nearest(ta, dev(q), 10)
+    _, ik, dk_ = abx.query_nearest(tk, dev(q), 10)
+    assert torch.equal(ia, ik) and torch.equal(da_, dk_)
+    check_nearest(orc, pts, 0, q[::997], 10, ia.cpu().numpy()[::997], da_.cpu().numpy()[::997])
