@@ -33,7 +33,7 @@ def test_morton_codes_bit_exact(orc, kind, bits):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 100_003])
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 6143, 6144, 6145, 12_289, 100_003])
 @pytest.mark.parametrize("key_bits", [30, 63])
 def test_radix_sort_stable(n, key_bits):
     rng = np.random.default_rng(n + key_bits)
