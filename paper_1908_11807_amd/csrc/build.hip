@@ -654,24 +654,25 @@ size_t refit_frontier_cap(int64_t n) {
 // ------------------------------------------------------------ Q16 nodes
 // The 16-bit code of a box's lower (upper) face: the largest (smallest) q
 // whose dequantised value fmaf(q, s, o) is <= x (>= x), so the decoded box
-// contains the exact one and is the tightest such box.  dequantisation is
-// monotone in q, so the estimate from inv = 1/s (any nearby start) is moved
-// to that q by the two loops; they take a step or two at most.
-__device__ __forceinline__ uint32_t q_clamp(double e) {
-  return e <= 0.0 ? 0u : (e >= (double)kQ16Max ? (uint32_t)kQ16Max : (uint32_t)e);
+// contains the exact one and is the tightest such box.  Dequantisation is
+// monotone in q, so any nearby start reaches that q through the two loops:
+// the float estimate (x - o) * (1/s) is within a small fraction of a step
+// for x inside the scene box, and the loops take a step or two at most.
+__device__ __forceinline__ uint32_t q_clamp(float e) {
+  return e <= 0.0f ? 0u : (e >= (float)kQ16Max ? (uint32_t)kQ16Max : (uint32_t)e);
 }
 
-__device__ __forceinline__ uint32_t q_lo(float x, float o, float s, double inv) {
+__device__ __forceinline__ uint32_t q_lo(float x, float o, float s, float inv) {
   if (s == 0.0f) return 0;
-  uint32_t q = q_clamp(floor(((double)x - (double)o) * inv));
+  uint32_t q = q_clamp(floorf((x - o) * inv));
   while (q > 0 && deq(q, s, o) > x) --q;
   while (q < (uint32_t)kQ16Max && deq(q + 1, s, o) <= x) ++q;
   return q;
 }
 
-__device__ __forceinline__ uint32_t q_hi(float x, float o, float s, double inv) {
+__device__ __forceinline__ uint32_t q_hi(float x, float o, float s, float inv) {
   if (s == 0.0f) return 0;
-  uint32_t q = q_clamp(ceil(((double)x - (double)o) * inv));
+  uint32_t q = q_clamp(ceilf((x - o) * inv));
   while (q < (uint32_t)kQ16Max && deq(q, s, o) < x) ++q;
   while (q > 0 && deq(q - 1, s, o) >= x) --q;
   return q;
@@ -690,13 +691,12 @@ __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restr
   if (i >= ni) return;
   const float *f = reinterpret_cast<const float *>(src + i);
   const int4 d = src[i].d;
-  float o[3], sc[3];
-  double inv[3];
+  float o[3], sc[3], inv[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     o[a] = hdr->q_origin[a];
     sc[a] = hdr->q_scale[a];
-    inv[a] = sc[a] != 0.0f ? 1.0 / (double)sc[a] : 0.0;
+    inv[a] = sc[a] != 0.0f ? 1.0f / sc[a] : 0.0f;
   }
   uint32_t w[6];
 #pragma unroll
