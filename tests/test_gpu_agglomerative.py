@@ -124,6 +124,18 @@ def _sorted_rows(a):
     return a[np.lexsort(a.T[::-1])]
 
 
+@pytest.mark.parametrize("n", [524_288, 524_289])
+def test_group_edges_same_boxes(n):
+    pts = datagen.clusters(n, 81)
+    tk = abx.bvh_build(dev(pts), node_format="fp32")
+    ta = abx.bvh_build(dev(pts), node_format="fp32", hierarchy="agglomerative")
+    assert ta.layout.height == tk.layout.height
+    da, dk = decode_tree(ta), decode_tree(tk)
+    rows_a = _sorted_rows(np.concatenate([da["boxes_l"], da["boxes_r"]]))
+    rows_k = _sorted_rows(np.concatenate([dk["boxes_l"], dk["boxes_r"]]))
+    assert np.array_equal(rows_a, rows_k)
+
+
 @pytest.mark.parametrize("fmt", ["fp32", "q16"])
 def test_large_tree_all_build_phases(orc, fmt):
     # 1.3e6 leaves: 159 chunks in three groups of 64 (the last ragged), so the

@@ -124,6 +124,13 @@ def test_build_all_refit_phases(orc, kind, fmt):
     assert t.height >= 2
 
 
+@pytest.mark.parametrize("n", [524_287, 524_288, 524_289, 532_481])
+def test_build_group_edges(orc, n):
+    # one group of 64 chunks exactly, one leaf either side, and one leaf past
+    # the first chunk of the second group: the top pass runs only past 524 288
+    _check_tree_vs_oracle(orc, datagen.clusters(n, 90), 0, 21, "fp32")
+
+
 def test_build_duplicates_and_degenerate_axis(orc):
     rng = np.random.default_rng(1)
     pts = rng.integers(0, 4, size=(3000, 3)).astype(np.float32)   # heavy duplicates
