@@ -184,7 +184,7 @@ def main():
         if cnt:
             ktimes[name] = dict(ms_per_launch=ms / cnt, launches_per_step=cnt / args.steps)
     # the nearest traversal is two launches (one lane per query, then one
-    # wavefront per heavy query); the roofline takes them together
+    # workgroup per heavy query); the roofline takes them together
     if "nearest" in ktimes and "nearest_coop" in ktimes:
         ktimes["nearest+coop"] = dict(
             ms_per_launch=ktimes["nearest"]["ms_per_launch"] + ktimes["nearest_coop"]["ms_per_launch"],

@@ -233,13 +233,15 @@ abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, 
 /* -- load balance of nearest queries ------------------------------------------
  * A nearest query is first walked by one lane (the paper's batched mode).  A
  * walk that exceeds `visits` internal-node visits is abandoned and the query
- * is answered again by a whole wavefront (64 lanes sharing one query: the
- * frontier is split among the lanes, their pruning bound is shared, their
- * candidate lists are merged exactly).  Results do not depend on the value.
+ * is answered again by a whole workgroup (16 wavefronts, 8 for k > 16, i.e.
+ * 1024 or 512 lanes sharing one query: a breadth-first frontier is split among
+ * the lanes, their pruning bound is shared, their candidate lists are merged
+ * exactly), starting from the bound the lane had reached.  Results do not
+ * depend on the value.  (k > 32 is walked by one lane throughout.)
  * abx_set_nearest_budget sets the process-wide budget (<= 0: unlimited, i.e.
  * one lane per query throughout) and returns the previous one.  Default 24576.
  * A batch of m queries uses min(budget, max(512, m / 16)): small batches
- * leave the GPU idle and hand heavy queries to whole wavefronts sooner. */
+ * leave the GPU idle and hand heavy queries to whole workgroups sooner. */
 int64_t abx_set_nearest_budget(int64_t visits);
 
 /* -- traversal statistics ---------------------------------------------------

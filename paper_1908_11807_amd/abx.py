@@ -680,7 +680,7 @@ class Server:
 
 def set_nearest_budget(visits):
     """Node visits before a nearest query moves to the cooperative (one
-    wavefront per query) pass; <= 0 keeps every query on one lane.  Returns
+    workgroup per query) pass; <= 0 keeps every query on one lane.  Returns
     the previous value."""
     return int(_lib().abx_set_nearest_budget(int(visits)))
 

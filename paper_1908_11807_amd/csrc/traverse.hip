@@ -539,7 +539,7 @@ abx_status nearest_fmt(const abx_bvh *b, const float *pts, int64_t m, const int3
 }
 
 // Small batches leave most of the GPU idle, so their heavy queries are
-// better served early by whole wavefronts: the one-lane budget shrinks with
+// better served early by whole workgroups: the one-lane budget shrinks with
 // the batch (never below 512 visits, never above the configured budget).
 int64_t effective_budget(int64_t budget, int64_t m) {
   const int64_t b = std::max<int64_t>(512, m / 16);
