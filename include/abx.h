@@ -214,9 +214,9 @@ abx_status abx_query_spatial_1p(const abx_bvh *bvh, const abx_predicates *preds,
  *   smaller index); missing results are purged, so every row has length
  *   k' = min(k, n).  offsets[i] = i * k'; indices and distances are [m, k']
  *   in the caller's query order; distances are float32 Euclidean (point to
- *   box for box primitives).  No host synchronisation.  1 <= k <= 32 keeps
+ *   box for box primitives).  No host synchronisation.  1 <= k <= 64 keeps
  *   the candidates in registers (one lane per query, heavy queries handed to
- *   whole workgroups); 33 <= k <= 128 keeps them in per-lane LDS max-heaps
+ *   whole workgroups); 65 <= k <= 128 keeps them in per-lane LDS max-heaps
  *   (one lane per query throughout); larger k returns ABX_ERR_UNSUPPORTED.
  *   Per axis the gap is max(lo - q, q - hi, 0) with IEEE max, which drops a
  *   NaN operand: a NaN query coordinate contributes no gap on its axis (the
@@ -237,7 +237,7 @@ abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, 
  * 1024 or 512 lanes sharing one query: a breadth-first frontier is split among
  * the lanes, their pruning bound is shared, their candidate lists are merged
  * exactly), starting from the bound the lane had reached.  Results do not
- * depend on the value.  (k > 32 is walked by one lane throughout.)
+ * depend on the value.  (k > 64 is walked by one lane throughout.)
  * abx_set_nearest_budget sets the process-wide budget (<= 0: unlimited, i.e.
  * one lane per query throughout) and returns the previous one.  Default 24576.
  * A batch of m queries uses min(budget, max(512, m / 16)): small batches

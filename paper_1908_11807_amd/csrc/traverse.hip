@@ -149,7 +149,9 @@ __attribute__((amdgpu_waves_per_eu(nearest_waves_per_eu(K)))) void k_nearest(Tre
 }
 
 // ------------------------------------------------------------ large k
-// k = 33..128: each lane keeps its candidates in an LDS max-heap (root = the
+// k = 65..128 (register lists serve k <= 64: 64 keys take 128 registers, the
+// most that leaves two wavefronts per SIMD): each lane keeps its candidates
+// in an LDS max-heap (root = the
 // current k-th candidate; the heap is the paper's bounded priority list,
 // section 2.2), one wavefront per workgroup, entry e of lane l at e * 64 + l
 // so that a wavefront's accesses fall in distinct banks.  The walk is the
@@ -535,7 +537,9 @@ abx_status nearest_fmt(const abx_bvh *b, const float *pts, int64_t m, const int3
   if (k <= 8) return nearest_k<KIND, FMT, 8>(b, pts, m, order, k, idx, dist, stats, ns, s);
   if (k <= 10) return nearest_k<KIND, FMT, 10>(b, pts, m, order, k, idx, dist, stats, ns, s);
   if (k <= 16) return nearest_k<KIND, FMT, 16>(b, pts, m, order, k, idx, dist, stats, ns, s);
-  return nearest_k<KIND, FMT, 32>(b, pts, m, order, k, idx, dist, stats, ns, s);
+  if (k <= 32) return nearest_k<KIND, FMT, 32>(b, pts, m, order, k, idx, dist, stats, ns, s);
+  if (k <= 48) return nearest_k<KIND, FMT, 48>(b, pts, m, order, k, idx, dist, stats, ns, s);
+  return nearest_k<KIND, FMT, kMaxRegK>(b, pts, m, order, k, idx, dist, stats, ns, s);
 }
 
 // Small batches leave most of the GPU idle, so their heavy queries are
@@ -551,7 +555,7 @@ abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const i
                           float *heavy_bound, uint32_t *counters, int64_t budget, hipStream_t s) {
   if (m == 0 || k == 0) return ABX_OK;
   if (k > kMaxHeapK) return ABX_ERR_UNSUPPORTED;
-  if (k > 32) {
+  if (k > kMaxRegK) {
     if (b->kind == ABX_PRIM_POINTS) {
       if (b->format == ABX_NODES_FP32)
         return nearest_heap<ABX_PRIM_POINTS, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, s);

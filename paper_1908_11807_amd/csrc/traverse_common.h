@@ -13,12 +13,13 @@ constexpr int kTravBlock = 256;
 constexpr int kMaxDepth = 128;
 constexpr int kLdsDepthSpatial = 16;
 constexpr int kLdsDepthNearest = 8;
-constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 33..128)
+constexpr int kMaxRegK = 64;    // largest k kept in registers (lists of 1..64 keys)
+constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 65..128)
 
 // Occupancy target of the one-lane nearest pass (waves per SIMD).  Six beat
 // eight at k = 10 on the C3 shell (fewer walks competing for L2, no spills);
 // the k = 32 list alone takes 64 registers.
-constexpr int nearest_waves_per_eu(int K) { return K > 16 ? 3 : (K > 10 ? 4 : (K > 4 ? 6 : 8)); }
+constexpr int nearest_waves_per_eu(int K) { return K > 48 ? 2 : (K > 16 ? 3 : (K > 10 ? 4 : (K > 4 ? 6 : 8))); }
 
 struct TreeArgs {
   const void *nodes;

@@ -359,6 +359,26 @@ def test_nearest_cooperative_pass(orc, budget, fmt):
         abx.set_nearest_budget(old)
 
 
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+def test_nearest_cooperative_pass_large_lists(orc, fmt):
+    # the 48- and 64-key lists through the cooperative pass (budget 1), equal
+    # to the one-lane walk bit for bit
+    pts = datagen.shell(20_000, 63, 1 - 5e-3, 1 + 5e-3)
+    q = datagen.uniform_cube(1501, 64, -1.0, 1.0)
+    t = abx.bvh_build(dev(pts), node_format=fmt)
+    old = abx.set_nearest_budget(0)
+    try:
+        for k in (40, 64):
+            abx.set_nearest_budget(0)
+            _, i1, d1 = abx.query_nearest(t, dev(q), k)
+            abx.set_nearest_budget(1)
+            _, ik, dk = abx.query_nearest(t, dev(q), k)
+            assert np.array_equal(host(ik), host(i1)) and np.array_equal(host(dk), host(d1))
+            check_nearest(orc, pts, 0, q, k, host(ik), host(dk), rows=np.arange(0, 1501, 7))
+    finally:
+        abx.set_nearest_budget(old)
+
+
 def test_nearest_cooperative_boxes_and_ties(orc):
     pts = np.repeat(datagen.uniform_cube(2000, 71), 3, axis=0)     # triplicated points
     boxes = datagen.boxes_around(datagen.clusters(6000, 72), 73, 0.01)
@@ -400,9 +420,9 @@ def test_nearest_nan_and_infinite_queries(orc):
         assert cnt[7] > 0 and cnt[8] == 0 and cnt[9] == 0
 
 
-@pytest.mark.parametrize("k", [33, 64, 100, 128])
-def test_nearest_large_k_heaps(orc, k):
-    # 33 <= k <= 128: candidates in per-lane LDS max-heaps
+@pytest.mark.parametrize("k", [33, 48, 49, 64, 65, 100, 128])
+def test_nearest_large_k(orc, k):
+    # 33..64: register lists of 48 or 64 keys; 65..128: per-lane LDS max-heaps
     pts = datagen.clusters(20_000, 91)
     q = datagen.uniform_cube(2_001, 92)
     boxes = datagen.boxes_around(pts, 93, 0.003)
