@@ -329,7 +329,8 @@ abx_status abx_forest_query_nearest_sizes(const abx_forest *f, const abx_forest_
  * (distance, index); indices are tree-local (0 .. n_t-1).  Rows follow the
  * caller's query order; row i has min(k, n_t) entries starting at
  * offsets[i]; offsets[M] = total.  `cfg` may be NULL (the tuned shape of
- * abx_forest_autotune if any, else a default).  1 <= k <= 32. */
+ * abx_forest_autotune if any, else a default).  1 <= k <= 64 (larger k:
+ * ABX_ERR_UNSUPPORTED). */
 abx_status abx_forest_query_nearest(const abx_forest *f, const abx_forest_queries *q, int32_t k,
                                     const abx_forest_config *cfg, void *scratch, size_t scratch_bytes,
                                     int32_t *offsets /*[M+1]*/, int32_t *indices, float *distances,

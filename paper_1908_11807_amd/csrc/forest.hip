@@ -381,7 +381,9 @@ abx_status forest_nearest_fmt(const TreeArgs &t, const ForestMap &map, const flo
   if (k <= 8) ABX_FK(8);
   if (k <= 10) ABX_FK(10);
   if (k <= 16) ABX_FK(16);
-  ABX_FK(32);
+  if (k <= 32) ABX_FK(32);
+  if (k <= 48) ABX_FK(48);
+  ABX_FK(kMaxRegK);
 #undef ABX_FK
 }
 
@@ -391,7 +393,7 @@ abx_status forest_launch_nearest(const TreeArgs &t, int format, const int64_t *p
                                  float *dist, int32_t *heavy_q, float *heavy_bound, uint32_t *counters,
                                  int blocks_per_cu, int grab, int64_t budget, hipStream_t s) {
   if (M == 0 || k == 0) return ABX_OK;
-  if (k > 32) return ABX_ERR_UNSUPPORTED;
+  if (k > kMaxRegK) return ABX_ERR_UNSUPPORTED;
   const ForestMap map{poff, qtree, roots, tscene, offsets, k};
   const HeavyList heavy{heavy_q, heavy_bound, counters};
   ABX_TRY(fill_u32(counters, 0, 3, s));  // heavy count, next heavy, tile queue

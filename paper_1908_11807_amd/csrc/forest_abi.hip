@@ -305,7 +305,7 @@ abx_status abx_forest_query_nearest(const abx_forest *f, const abx_forest_querie
                                     abx_stream_t stream) {
   int64_t tot = 0;
   ABX_TRY(forest_query_check(f, q, k, &tot));
-  if (k > 32) return ABX_ERR_UNSUPPORTED;
+  if (k > kMaxRegK) return ABX_ERR_UNSUPPORTED;
   const int T = f->T;
   const int64_t M = q->offsets_host[T];
   const ForestQueryLayout L = forest_query_layout(T, M);

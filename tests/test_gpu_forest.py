@@ -46,7 +46,7 @@ def check_forest(orc, pts, off, qs, qoff, k, offsets, idx, dist, rows_per_tree=N
 
 
 @pytest.mark.parametrize("fmt", ["fp32", "q16"])
-@pytest.mark.parametrize("k", [1, 10, 16])
+@pytest.mark.parametrize("k", [1, 10, 16, 40, 64])
 def test_forest_nearest_matches_oracle(orc, fmt, k):
     sizes = [0, 1, 3, 9, 17, 100, 1000, 2500, 40, 5000, 1, 777]
     qsizes = [5, 7, 0, 30, 64, 65, 300, 129, 11, 400, 3, 250]
@@ -125,3 +125,11 @@ def test_forest_check_flags_nan():
     with pytest.raises(abx.AbxError) as e:
         plan.check()
     assert e.value.status == abx.ERR_INVALID_INPUT
+
+
+def test_forest_k_above_64_unsupported():
+    pts, off, qs, qoff = make_forest(21, [100, 200], [10, 20])
+    plan = abx.ForestPlan(torch.from_numpy(pts).cuda(), off, torch.from_numpy(qs).cuda(), qoff, 65, "q16")
+    with pytest.raises(abx.AbxError) as e:
+        plan.query()
+    assert e.value.status == abx.ERR_UNSUPPORTED
