@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--compare-formats", action="store_true",
                     help="also measure the other node format's query rates (untimed block)")
-    ap.add_argument("--serve-requests", type=int, default=400,
+    ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per load level of the serving block (0: skip it)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--trees", type=int, default=256, help="forest size (C4)")
@@ -465,7 +465,8 @@ def bench_serving(args, standalone):
         return np.array(lat), qsum, last - t0
 
     nreq = max(args.serve_requests, 20)
-    run(make(min(nreq, 100), 700, 1.0), abx.server_now(), paced=False)   # warm-up
+    nwarm = min(nreq, 1000)
+    run(make(nwarm, 700, 1.0), abx.server_now(), paced=False)   # warm-up
     lat, qsum, span = run(make(nreq, 701, 1.0), abx.server_now(), paced=False)
     sat_rps = nreq / span
     out = {"saturated_requests_per_s": round(sat_rps, 1), "saturated_queries_per_s": round(qsum / span, 1),
@@ -485,7 +486,7 @@ def bench_serving(args, standalone):
     if standalone:
         top = out["loads"][-1]
         return {"metric": "serving p99 batch latency at 95% load (4 x 1e7-point trees)",
-                "value": top["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": nreq, "warmup": 100,
+                "value": top["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": nreq, "warmup": nwarm,
                 "ms_per_step": top["p50_ms"], "higher_is_better": False, "scaling": "weak",
                 "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                 "config": {"workload": "C5: 4 device-resident trees of 1e7 points (2 cube, 2 shell), "

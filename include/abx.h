@@ -366,7 +366,10 @@ abx_status abx_graph_destroy(void *graph_exec);
  * a pinned host arena the server allocates at creation and stay valid until
  * abx_server_release.  Every request is answered by the same kernels as the
  * plain entry points, so its result does not depend on what else is in
- * flight.  Times are seconds on abx_server_now()'s steady clock.
+ * flight.  Radius requests, and nearest requests of fewer than 4096
+ * queries, are walked in the caller's order; larger nearest requests are
+ * Morton-ordered first (at request sizes the ordering pays only for long
+ * nearest walks).  Times are seconds on abx_server_now()'s steady clock.
  * Reservations (bytes, 256-B granules): queries 12m + query scratch +
  * nearest 8mk' | radius offsets 4(m+1), then 4*total for the fill.
  * `simulate` = 1 runs the scheduler without HIP (each phase lasts
