@@ -218,6 +218,22 @@ def main():
         roof = dict(kernel=dom, bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=None, traffic=None)
 
+    # one-pass radius search (the paper's buffer_size scheme): buffer = the
+    # largest row, so one traversal answers the batch
+    row_max = int(torch.diff(off).max().item()) if m > 0 else 0
+    bsz = max(row_max, 1)
+    t1p = []
+    for i in range(4):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        _, _, trav = abx.query_spatial_1p(t, qs, bsz, radius=r)
+        b.record()
+        b.synchronize()
+        if i:
+            t1p.append(a.elapsed_time(b))
+    radius_1p = dict(ms=round(float(np.median(t1p)), 3), buffer_size=bsz, traversals=trav,
+                     speedup_vs_2p=round(rad_ms / float(np.median(t1p)), 3))
+
     # the other two phases against the same HBM peak (algorithmic bytes)
     bpp = build_bytes_per_prim(args.nodes, args.morton_bits)
     rad_bytes = alg["spatial_count"] + alg["spatial_fill"]
@@ -251,6 +267,7 @@ def main():
                             "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "radius_results": hits,
         "phase_rooflines": phase_rooflines,
+        "radius_1p": radius_1p,
         "tree_height": t.height,
         "kernels": {kn: {kk: round(v, 4) for kk, v in d.items()} for kn, d in ktimes.items()},
         "roofline": roof,
@@ -336,6 +353,13 @@ def bench_paper(args):
             cnt = torch.diff(off).cpu().numpy()
             row["neighbours"] = dict(mean=round(float(cnt.mean()), 3), min=int(cnt.min()),
                                      max=int(cnt.max()))
+            # one pass (Morton-ordered queries): buffer = the largest row (one
+            # traversal), and a fixed buffer of 16 (overflow: second traversal)
+            for tag, bsz in (("1p_max", max(int(cnt.max()), 1)), ("1p_16", 16)):
+                ms1, (_, _, trav) = timed(lambda: abx.query_spatial_1p(t, qs, bsz, radius=r))
+                row[f"radius_ms_{tag}"] = round(ms1, 4)
+                row[f"radius_qps_{tag}"] = round(p / ms1 * 1e3, 1)
+                row[f"traversals_{tag}"] = trav
             rows.append(row)
             print(json.dumps(row), file=sys.stderr, flush=True)
             del t, pts, qs
