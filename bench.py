@@ -80,9 +80,10 @@ def algorithmic_bytes(stats, node_b, leaf_b, per_query_fixed):
     return int(per_query_fixed * s.shape[0] + node_b * s[:, 0].sum() + leaf_b * s[:, 1].sum())
 
 
-def build_bytes_per_prim(node_format, morton_bits, kind_width=3):
+def build_bytes_per_prim(node_format, morton_bits, kind_width=3, hierarchy="karras"):
     """Algorithmic bytes of one build, per point primitive (Karras hierarchy,
-    two-phase refit, 8-bit radix digits)."""
+    two-phase refit, 8-bit radix digits; Q16 Karras trees also renumber their
+    nodes depth-first)."""
     keyb = 8 if morton_bits > 10 else 4          # 63- or 30-bit Morton keys
     passes = 8 if morton_bits > 10 else 4        # 8-bit digits
     w = 4 * kind_width                           # 12 B point (24 B box)
@@ -95,6 +96,10 @@ def build_bytes_per_prim(node_format, morton_bits, kind_width=3):
     b += 4 + 4 + 64 + 28                         # refit, node: parent, range end, node, sibling
     if node_format == "q16":
         b += 64 + 32                             # quantise: read FP32 node, write Q16 node
+        if hierarchy == "karras":
+            b += 4 + 8                           # depth-first order: parent link, first word
+            b += 7 * (8 + 8 + 8)                 # 7 pointer-jumping rounds: own, ancestor's, out
+            b += 8 + 4                           # quantise: the node's word and range end
     return b
 
 
@@ -235,7 +240,7 @@ def main():
                      speedup_vs_2p=round(rad_ms / float(np.median(t1p)), 3))
 
     # the other two phases against the same HBM peak (algorithmic bytes)
-    bpp = build_bytes_per_prim(args.nodes, args.morton_bits)
+    bpp = build_bytes_per_prim(args.nodes, args.morton_bits, hierarchy=args.hierarchy)
     rad_bytes = alg["spatial_count"] + alg["spatial_fill"]
     phase_rooflines = {
         "build": dict(bytes_per_prim=bpp, achieved=round(bpp * n / (build_ms * 1e-3) / 1e9, 1),

@@ -128,6 +128,10 @@ typedef struct {
   int32_t height;         /* longest root-to-leaf edge count (0 if n <= 1)  */
   int32_t hierarchy;      /* abx_hierarchy the tree was built with          */
   int32_t root;           /* internal node at the root (n >= 2)             */
+  int32_t node_order;     /* 0: the hierarchy's own numbering; 1: depth-
+                             first (Q16 Karras trees): root 0, a node's left
+                             child right after it, its right child after the
+                             left subtree.  Queries do not depend on it.    */
   float scene[6];         /* scene box lo xyz, hi xyz (section 2.1)         */
   size_t nodes_offset;    /* byte offset of internal node 0 in tree memory */
   size_t node_bytes;      /* 64 (FP32) or 32 (Q16)                          */

@@ -105,7 +105,7 @@ REQ_RADIUS, REQ_NEAREST = 0, 1
 class Layout(C.Structure):
     _fields_ = [("n", C.c_int64), ("kind", C.c_int32), ("node_format", C.c_int32),
                 ("morton_bits", C.c_int32), ("height", C.c_int32), ("hierarchy", C.c_int32),
-                ("root", C.c_int32), ("scene", C.c_float * 6),
+                ("root", C.c_int32), ("node_order", C.c_int32), ("scene", C.c_float * 6),
                 ("nodes_offset", C.c_size_t), ("node_bytes", C.c_size_t),
                 ("leaves_offset", C.c_size_t), ("leaf_bytes", C.c_size_t),
                 ("q16_origin", C.c_float * 3), ("q16_scale", C.c_float * 3)]

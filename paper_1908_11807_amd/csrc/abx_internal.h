@@ -30,7 +30,8 @@ struct TreeHeader {
   float inv_ext[3];   // Morton normalisation: 1/(hi-lo) or 0
   float q_origin[3];  // Q16 grid: x = fmaf(q, q_scale, q_origin)
   float q_scale[3];
-  int32_t bad;        // 1 if a coordinate was NaN or infinite
+  int32_t bad;        // 1: NaN/inf coordinate or inverted box; 2: Q16 grid overflow; 4: refit
+                      // bound or frontier exceeded; 8: depth-first order out of range
   int32_t height;     // longest root-to-leaf path (edges)
   int32_t root;       // internal node at the root (0 for the Karras numbering)
   int32_t pad[46];
@@ -169,6 +170,7 @@ struct abx_bvh {
   int64_t n;
   int32_t kind, format, morton_bits, height;
   int32_t hierarchy, root;  // construction used; internal node at the root
+  int32_t node_order;       // 0: the hierarchy's numbering, 1: depth-first
   float scene[6];
   float q_origin[3], q_scale[3];
   char *tree;  // device base

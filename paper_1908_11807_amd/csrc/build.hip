@@ -682,13 +682,37 @@ __device__ __forceinline__ uint32_t q_hi(float x, float o, float s, float inv) {
 // boxes; in a point tree a leaf child's 12-byte slot holds the point's
 // float32 x, y, z instead (the traversal tells the two apart by the sign of
 // the reference), so point leaves need no second memory access.
+// depth-first index of node x from its finished pointer-jumping word (see
+// k_pre_*): first leaf of its range + left turns; -1 if x is out of range or
+// its path was longer than the rounds cover
+__device__ __forceinline__ int64_t pre_index(const uint64_t *__restrict__ w,
+                                             const int32_t *__restrict__ other_end, int64_t ni,
+                                             int64_t x) {
+  if (x < 0 || x >= ni) return -1;
+  const uint64_t v = w[x];
+  if ((int32_t)(uint32_t)v >= 0) return -1;
+  const int64_t j = other_end[x];
+  return (x < j ? x : j) + (int64_t)(v >> 32);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restrict__ src,
-                                                          int64_t ni,
-                                                          const TreeHeader *__restrict__ hdr,
+                                                          int64_t ni, TreeHeader *__restrict__ hdr,
+                                                          const uint64_t *__restrict__ pre_w,
+                                                          const int32_t *__restrict__ other_end,
                                                           NodeQ16 *__restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ni) return;
+  // with `pre_w`, node i goes to its depth-first slot and internal child
+  // references are renumbered the same way
+  int64_t slot = i;
+  if (pre_w) {
+    slot = pre_index(pre_w, other_end, ni, i);
+    if (slot < 0 || slot >= ni) {
+      atomicOr(&hdr->bad, 8);
+      return;
+    }
+  }
   const float *f = reinterpret_cast<const float *>(src + i);
   const int4 d = src[i].d;
   float o[3], sc[3], inv[3];
@@ -716,10 +740,77 @@ __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restr
       for (int h = 0; h < 3; ++h) w[3 * c + h] = q[2 * h] | (q[2 * h + 1] << 16);
     }
   }
+  int32_t ref[2] = {d.x, d.y};
+  if (pre_w) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      if (ref[c] >= 0) {
+        const int64_t r = pre_index(pre_w, other_end, ni, ref[c]);
+        if (r < 0 || r >= ni) atomicOr(&hdr->bad, 8);
+        ref[c] = (int32_t)r;
+      }
+  }
   NodeQ16 out;
   out.a = make_uint4(w[0], w[1], w[2], w[3]);
-  out.b = make_uint4(w[4], w[5], (uint32_t)d.x, (uint32_t)d.y);
-  dst[i] = out;
+  out.b = make_uint4(w[4], w[5], (uint32_t)ref[0], (uint32_t)ref[1]);
+  dst[slot] = out;
+}
+
+// ------------------------------------------------------ depth-first order
+// Nodes of a Karras tree renumbered in depth-first (pre-)order, left child
+// first: the root is 0 and a node's left child follows it, so a walk going
+// down touches consecutive nodes (C3 nearest walk 172 -> 166 ms).  The
+// preorder index of a node with leaf range [l, r] is l + the number of its
+// ancestors whose left subtree holds it: the internal nodes before it are its
+// ancestors plus those of the subtrees left of l, which hold l leaves in as
+// many subtrees as there are right turns on its path.  The count is a sum
+// along the path to the root, taken by pointer jumping: every round adds the
+// ancestor's partial sum and jumps twice as far (7 rounds cover paths of up
+// to 128 edges; trees are at most ~95 deep).
+constexpr int kPreRounds = 7;
+
+// one 64-bit word per node: left turns counted so far (high half) and the
+// ancestor to add next (low half, -1 when the root has been passed), so a
+// round gathers one word per node
+__global__ __launch_bounds__(kBuildBlock) void k_pre_init(const int32_t *__restrict__ parent_int,
+                                                          int64_t ni, uint64_t *__restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ni) return;
+  const int32_t pp = i == 0 ? -1 : parent_int[i];
+  const uint32_t val = pp >= 0 && (pp & 1) == 0 ? 1u : 0u;  // a left child
+  const int32_t anc = pp >= 0 ? pp >> 1 : -1;
+  w[i] = ((uint64_t)val << 32) | (uint32_t)anc;
+}
+
+__global__ __launch_bounds__(kBuildBlock) void k_pre_jump(const uint64_t *__restrict__ in, int64_t ni,
+                                                          uint64_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ni) return;
+  const uint64_t x = in[i];
+  const int32_t a = (int32_t)(uint32_t)x;
+  if (a >= 0 && a < ni) {
+    const uint64_t y = in[a];
+    out[i] = (((x >> 32) + (y >> 32)) << 32) | (uint32_t)y;
+  } else {
+    out[i] = (x & 0xffffffff00000000ull) | 0xffffffffu;
+  }
+}
+
+// scratch: 2 * ni words; returns (through *result) the buffer holding the
+// finished words, which k_quantise turns into depth-first indices
+abx_status launch_preorder(const int32_t *parent_int, int64_t ni, uint64_t *work,
+                           const uint64_t **result, hipStream_t s) {
+  *result = nullptr;
+  if (ni <= 0) return ABX_OK;
+  const unsigned g = grid_for(ni, kBuildBlock);
+  uint64_t *buf[2] = {work, work + ni};
+  ABX_TRY(launch("preorder", s, [&] { k_pre_init<<<g, kBuildBlock, 0, s>>>(parent_int, ni, buf[0]); }));
+  for (int r = 0; r < kPreRounds; ++r) {
+    const int a = r & 1, b = a ^ 1;
+    ABX_TRY(launch("preorder", s, [&] { k_pre_jump<<<g, kBuildBlock, 0, s>>>(buf[a], ni, buf[b]); }));
+  }
+  *result = buf[kPreRounds & 1];
+  return ABX_OK;
 }
 
 // ------------------------------------------------------------ host launchers
@@ -818,16 +909,17 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
   });
 }
 
-abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, const TreeHeader *hdr,
-                           NodeQ16 *dst, hipStream_t s) {
+abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, TreeHeader *hdr,
+                           const uint64_t *pre_w, const int32_t *other_end, NodeQ16 *dst,
+                           hipStream_t s) {
   if (ni <= 0) return ABX_OK;
   const unsigned g = grid_for(ni, kBuildBlock);
   if (kind == ABX_PRIM_POINTS)
     return launch("quantise", s, [&] {
-      k_quantise<ABX_PRIM_POINTS><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, dst);
+      k_quantise<ABX_PRIM_POINTS><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, pre_w, other_end, dst);
     });
   return launch("quantise", s, [&] {
-    k_quantise<ABX_PRIM_BOXES><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, dst);
+    k_quantise<ABX_PRIM_BOXES><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, pre_w, other_end, dst);
   });
 }
 

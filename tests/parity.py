@@ -94,6 +94,34 @@ def check_nearest(orc, prims, kind, queries, k, gpu_idx, gpu_dist, rows=None):
 
 
 # ---------------------------------------------------------------- trees
+def _karras_numbering(rows, refs, n, inv):
+    """Node rows of a depth-first numbered tree (root 0, left child next,
+    right child after the left subtree) moved to the Karras numbering (root
+    0, the children of a node split at gamma are nodes gamma and gamma+1),
+    with internal child references rewritten; leaf references (~primitive)
+    are kept.  `inv` maps primitive -> sorted position."""
+    ni = rows.shape[0]
+    kid = np.full(ni, -1, np.int64)
+    kid[0] = 0
+    cur, lo = np.array([0], np.int64), np.array([0], np.int64)
+    while cur.size:
+        lr, rr = refs[cur, 0], refs[cur, 1]
+        gamma = np.where(lr < 0, inv[np.clip(~lr, 0, n - 1)],
+                         np.where(rr < 0, inv[np.clip(~rr, 0, n - 1)] - 1, rr - cur - 1 + lo))
+        ml, mr = lr >= 0, rr >= 0
+        kid[lr[ml]] = gamma[ml]
+        kid[rr[mr]] = gamma[mr] + 1
+        cur = np.concatenate([lr[ml], rr[mr]])
+        lo = np.concatenate([lo[ml], gamma[mr] + 1])
+    assert np.array_equal(np.sort(kid), np.arange(ni)), "depth-first numbering is not a tree order"
+    new_refs = np.where(refs >= 0, kid[np.clip(refs, 0, ni - 1)], refs)
+    out = np.empty_like(rows)
+    out[kid] = rows
+    out_refs = np.empty_like(new_refs)
+    out_refs[kid] = new_refs
+    return out, out_refs
+
+
 def decode_tree(bvh):
     """Child kinds/indices (leaves by sorted position, as the hierarchy
     numbers them), permutation, node boxes and (for Q16) exact leaf boxes
@@ -112,10 +140,6 @@ def decode_tree(bvh):
         out["boxes_r"] = f[:, 6:12].copy()
         out["perm"] = leaves.view(np.int32).astype(np.int64)
     else:
-        u = nodes.view(np.uint16).reshape(ni, 16)
-        refs = nodes.view(np.int32).reshape(ni, 8)[:, 6:8]
-        out["q_l"] = u[:, 0:6].astype(np.uint32)
-        out["q_r"] = u[:, 6:12].astype(np.uint32)
         if bvh.kind == 0:
             out["perm"] = leaves.view(np.int32).astype(np.int64)
         else:
@@ -125,6 +149,18 @@ def decode_tree(bvh):
             perm[pos] = np.arange(n)
             out["perm"] = perm
             out["leaf_boxes"] = rec[perm, :6].copy()
+        if getattr(lay, "node_order", 0) == 1 and ni > 0:
+            inv0 = np.full(n, 0, np.int64)
+            inv0[out["perm"]] = np.arange(n)
+            rows, r2 = _karras_numbering(nodes.reshape(ni, 32), nodes.view(np.int32).reshape(ni, 8)[:, 6:8]
+                                         .astype(np.int64), n, inv0)
+            rows = rows.copy()
+            rows.view(np.int32).reshape(ni, 8)[:, 6:8] = r2.astype(np.int32)
+            nodes = rows.reshape(-1)
+        u = nodes.view(np.uint16).reshape(ni, 16)
+        refs = nodes.view(np.int32).reshape(ni, 8)[:, 6:8]
+        out["q_l"] = u[:, 0:6].astype(np.uint32)
+        out["q_r"] = u[:, 6:12].astype(np.uint32)
     perm = out["perm"]
     inv = np.full(n, -1, np.int64)
     ok = (perm >= 0) & (perm < n)
