@@ -35,6 +35,8 @@ PRED_WITHIN, PRED_INTERSECTS_BOX = 0, 1
 
 _FORMATS = {"fp32": NODES_FP32, "q16": NODES_Q16, NODES_FP32: NODES_FP32, NODES_Q16: NODES_Q16}
 _HIERARCHIES = {"karras": 0, "agglomerative": 1}
+_ORDERS = {"auto": 0, "build": 1, "depth_first": 2}
+ORDER_BUILD, ORDER_DEPTH_FIRST = 1, 2
 _PREDS = {"within": PRED_WITHIN, "intersects": PRED_INTERSECTS_BOX,
           PRED_WITHIN: PRED_WITHIN, PRED_INTERSECTS_BOX: PRED_INTERSECTS_BOX}
 
@@ -54,7 +56,8 @@ class Primitives(C.Structure):
 
 
 class BuildOptions(C.Structure):
-    _fields_ = [("node_format", C.c_int), ("morton_bits", C.c_int32), ("hierarchy", C.c_int32)]
+    _fields_ = [("node_format", C.c_int), ("morton_bits", C.c_int32), ("hierarchy", C.c_int32),
+                ("node_order", C.c_int32)]
 
 
 class Predicates(C.Structure):
@@ -262,18 +265,22 @@ class BVH:
             _LIB.abx_bvh_destroy(h)
 
 
-def bvh_build(prims, kind=None, node_format="fp32", morton_bits=21, hierarchy="karras"):
+def bvh_build(prims, kind=None, node_format="fp32", morton_bits=21, hierarchy="karras",
+              node_order="auto"):
     """Build the LBVH of ``prims`` (float32 CUDA tensor, [n,3] points or [n,6] boxes).
 
     ``hierarchy``: "karras" (per-node range search, then refit) or
-    "agglomerative" (hierarchy and refit in one bottom-up pass)."""
+    "agglomerative" (hierarchy and refit in one bottom-up pass).
+    ``node_order``: "auto", "build" (the hierarchy's numbering) or
+    "depth_first" (Q16 Karras trees)."""
     L = _lib()
     if kind is None:
         kind = PRIM_BOXES if (prims.dim() == 2 and prims.shape[-1] == 6) else PRIM_POINTS
     width = 3 if kind == PRIM_POINTS else 6
     p = _dev_f32(prims, width, "primitives")
     pr = Primitives(kind, p.data_ptr() if p.numel() else None, p.shape[0])
-    opt = BuildOptions(_FORMATS[node_format], int(morton_bits), _HIERARCHIES[hierarchy])
+    opt = BuildOptions(_FORMATS[node_format], int(morton_bits), _HIERARCHIES[hierarchy],
+                       _ORDERS[node_order])
     tb, sb = C.c_size_t(), C.c_size_t()
     _check(L.abx_bvh_build_sizes(C.byref(pr), C.byref(opt), C.byref(tb), C.byref(sb)),
            "abx_bvh_build_sizes")

@@ -111,8 +111,18 @@ abx_status check_build_args(const abx_primitives *p, const abx_build_options *o)
   if (bits != 10 && bits != 21) return ABX_ERR_INVALID_ARG;
   if (o && o->hierarchy != ABX_HIERARCHY_KARRAS && o->hierarchy != ABX_HIERARCHY_AGGLOMERATIVE)
     return ABX_ERR_INVALID_ARG;
+  if (o && o->node_order != ABX_ORDER_AUTO && o->node_order != ABX_ORDER_BUILD &&
+      o->node_order != ABX_ORDER_DEPTH_FIRST)
+    return ABX_ERR_INVALID_ARG;
+  if (o && o->node_order == ABX_ORDER_DEPTH_FIRST &&
+      (o->node_format != ABX_NODES_Q16 || o->hierarchy == ABX_HIERARCHY_AGGLOMERATIVE))
+    return ABX_ERR_UNSUPPORTED;
   return ABX_OK;
 }
+
+// automatic depth-first order from this many primitives: 2^22 points make
+// 128 MB of Q16 nodes, half the last-level cache (see abx_node_order)
+constexpr int64_t kDepthFirstMinN = int64_t(1) << 22;
 
 BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   BuildLayout L{};
@@ -123,7 +133,12 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   L.q16 = o && o->node_format == ABX_NODES_Q16;
   L.node_bytes = L.q16 ? sizeof(NodeQ16) : sizeof(NodeF32);
   L.boxrec = L.q16 && p->kind == ABX_PRIM_BOXES;
-  L.preorder = L.q16 && !(o && o->hierarchy == ABX_HIERARCHY_AGGLOMERATIVE);
+  {
+    const bool karras = !(o && o->hierarchy == ABX_HIERARCHY_AGGLOMERATIVE);
+    const int order = o ? o->node_order : ABX_ORDER_AUTO;
+    L.preorder = L.q16 && karras &&
+                 (order == ABX_ORDER_DEPTH_FIRST || (order == ABX_ORDER_AUTO && L.n >= kDepthFirstMinN));
+  }
   L.leaf_bytes = L.boxrec ? 32 : 4;
   size_t off = sizeof(TreeHeader);
   L.nodes_off = off;
@@ -434,7 +449,7 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
   b->morton_bits = L.bits;
   b->height = h.height;
   b->hierarchy = agglo ? ABX_HIERARCHY_AGGLOMERATIVE : ABX_HIERARCHY_KARRAS;
-  b->node_order = L.preorder && !agglo ? 1 : 0;
+  b->node_order = L.preorder ? ABX_ORDER_DEPTH_FIRST : ABX_ORDER_BUILD;
   b->root = h.root;
   std::memcpy(b->scene, h.scene, sizeof(b->scene));
   std::memcpy(b->q_origin, h.q_origin, sizeof(b->q_origin));

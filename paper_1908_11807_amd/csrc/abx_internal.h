@@ -170,7 +170,7 @@ struct abx_bvh {
   int64_t n;
   int32_t kind, format, morton_bits, height;
   int32_t hierarchy, root;  // construction used; internal node at the root
-  int32_t node_order;       // 0: the hierarchy's numbering, 1: depth-first
+  int32_t node_order;       // abx_node_order: BUILD or DEPTH_FIRST
   float scene[6];
   float q_origin[3], q_scale[3];
   char *tree;  // device base

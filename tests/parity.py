@@ -149,7 +149,7 @@ def decode_tree(bvh):
             perm[pos] = np.arange(n)
             out["perm"] = perm
             out["leaf_boxes"] = rec[perm, :6].copy()
-        if getattr(lay, "node_order", 0) == 1 and ni > 0:
+        if getattr(lay, "node_order", 0) == 2 and ni > 0:   # depth-first
             inv0 = np.full(n, 0, np.int64)
             inv0[out["perm"]] = np.arange(n)
             rows, r2 = _karras_numbering(nodes.reshape(ni, 32), nodes.view(np.int32).reshape(ni, 8)[:, 6:8]

@@ -168,3 +168,26 @@ def test_build_rejects_unknown_hierarchy():
     for h, want in ((0, abx.OK), (1, abx.OK), (2, abx.ERR_INVALID_ARG), (-1, abx.ERR_INVALID_ARG)):
         opt = abx.BuildOptions(abx.NODES_FP32, 21, h)
         assert L.abx_bvh_build_sizes(C.byref(ok), C.byref(opt), C.byref(tb), C.byref(sb)) == want
+
+
+def test_build_node_order_option():
+    abx, L = _lib()
+    tb, sb = C.c_size_t(), C.c_size_t()
+    ok = abx.Primitives(abx.PRIM_POINTS, 1, 5)
+    cases = (
+        (abx.NODES_Q16, 0, 0, abx.OK), (abx.NODES_Q16, 0, 1, abx.OK), (abx.NODES_Q16, 0, 2, abx.OK),
+        (abx.NODES_FP32, 0, 2, abx.ERR_UNSUPPORTED),    # depth-first order needs Q16 nodes
+        (abx.NODES_Q16, 1, 2, abx.ERR_UNSUPPORTED),     # and the Karras hierarchy
+        (abx.NODES_Q16, 0, 3, abx.ERR_INVALID_ARG), (abx.NODES_Q16, 0, -1, abx.ERR_INVALID_ARG))
+    for fmt, h, order, want in cases:
+        opt = abx.BuildOptions(fmt, 21, h, order)
+        assert L.abx_bvh_build_sizes(C.byref(ok), C.byref(opt), C.byref(tb), C.byref(sb)) == want, \
+            (fmt, h, order)
+    # the order's scratch is reserved only where it is used
+    big = abx.Primitives(abx.PRIM_POINTS, 1, 1 << 20)
+    sizes = []
+    for order in (1, 2):
+        opt = abx.BuildOptions(abx.NODES_Q16, 21, 0, order)
+        assert L.abx_bvh_build_sizes(C.byref(big), C.byref(opt), C.byref(tb), C.byref(sb)) == abx.OK
+        sizes.append(sb.value)
+    assert sizes[1] - sizes[0] >= 16 * ((1 << 20) - 1)

@@ -63,8 +63,10 @@ def test_radix_sort_with_values():
 
 # ---------------------------------------------------------------- construction
 
-def _check_tree_vs_oracle(orc, prims, kind, bits, fmt):
-    t = abx.bvh_build(dev(prims), kind=kind, node_format=fmt, morton_bits=bits)
+def _check_tree_vs_oracle(orc, prims, kind, bits, fmt, node_order="auto"):
+    t = abx.bvh_build(dev(prims), kind=kind, node_format=fmt, morton_bits=bits, node_order=node_order)
+    if node_order == "depth_first":
+        assert t.layout.node_order == abx.ORDER_DEPTH_FIRST
     ref = orc.build(prims, kind, bits)
     n = prims.shape[0]
     got = decode_tree(t)
@@ -106,21 +108,27 @@ def test_build_points_matches_oracle(orc, n, bits):
     _check_tree_vs_oracle(orc, datagen.uniform_cube(n, 100 + n), 0, bits, "fp32")
 
 
-@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+@pytest.mark.parametrize("fmt,order", [("fp32", "auto"), ("q16", "build"), ("q16", "depth_first")])
 @pytest.mark.parametrize("kind", [0, 1])
-def test_build_formats_and_kinds(orc, fmt, kind):
+def test_build_formats_and_kinds(orc, fmt, order, kind):
     pts = datagen.clusters(12_345, 9)
     prims = pts if kind == 0 else datagen.boxes_around(pts, 10, 0.003)
-    _check_tree_vs_oracle(orc, prims, kind, 21, fmt)
+    _check_tree_vs_oracle(orc, prims, kind, 21, fmt, order)
 
 
-@pytest.mark.parametrize("kind,fmt", [(0, "fp32"), (1, "q16")])
-def test_build_all_refit_phases(orc, kind, fmt):
+@pytest.mark.parametrize("n", [2, 3, 4, 1000, 8193])
+def test_build_depth_first_small(orc, n):
+    # depth-first node order down to the smallest trees (root 0, one node)
+    _check_tree_vs_oracle(orc, datagen.uniform_cube(n, 300 + n), 0, 21, "q16", "depth_first")
+
+
+@pytest.mark.parametrize("kind,fmt,order", [(0, "fp32", "auto"), (1, "q16", "auto"), (0, "q16", "depth_first")])
+def test_build_all_refit_phases(orc, kind, fmt, order):
     # 1.3e6 leaves: 159 chunks of 8192 in three groups of 64 (the last one
     # ragged), so the in-chunk, in-group and cross-group refit phases all run
     pts = datagen.shell(1_300_000, 77, 0.99, 1.01)
     prims = pts if kind == 0 else datagen.boxes_around(pts, 78, 0.001)
-    t = _check_tree_vs_oracle(orc, prims, kind, 21, fmt)
+    t = _check_tree_vs_oracle(orc, prims, kind, 21, fmt, order)
     assert t.height >= 2
 
 
@@ -298,15 +306,15 @@ def test_variants_bitwise_equal(orc):
     q = datagen.uniform_cube(20_000, 52, -1.0, 1.0)
     r = float(np.float32(0.02))
     res, csr = {}, None
-    for fmt in ("fp32", "q16"):
-        t = abx.bvh_build(dev(pts), node_format=fmt)
+    for fmt, order in (("fp32", "auto"), ("q16", "build"), ("q16", "depth_first")):
+        t = abx.bvh_build(dev(pts), node_format=fmt, node_order=order)
         for sq in (True, False):
             off, idx = abx.query_spatial(t, dev(q), radius=r, sort_queries=sq)
             o, i = host(off), host(idx)
             csr = csr or (o, i)
             rows = [tuple(sorted(i[o[j]:o[j + 1]].tolist())) for j in range(len(q))]
             _, ki, kd = abx.query_nearest(t, dev(q), 10, sort_queries=sq)
-            res[(fmt, sq)] = (o.tolist(), rows, host(ki).tobytes(), host(kd).tobytes())
+            res[(fmt, order, sq)] = (o.tolist(), rows, host(ki).tobytes(), host(kd).tobytes())
     first = next(iter(res.values()))
     for v in res.values():
         assert v == first
