@@ -48,7 +48,8 @@ abx_status launch_spatial_compact(const OnePass &op, int64_t m, const int32_t *o
                                   int32_t *info, int64_t max_count, hipStream_t s);
 abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order,
                           int k, int32_t *idx, float *dist, int32_t *stats, int32_t *heavy_q,
-                          float *heavy_bound, uint32_t *counters, int64_t budget, hipStream_t s);
+                          float *heavy_bound, uint32_t *counters, int32_t *heavy_state,
+                          int64_t state_cap, int64_t budget, hipStream_t s);
 int max_tree_depth();
 
 // node visits after which a nearest query leaves the one-lane pass for the
@@ -180,10 +181,12 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
 
 // ---------------------------------------------------------------- queries
 struct QueryLayout {
-  size_t codes, sorted, order, counts, total, scan, sort, heavy_q, heavy_bound, bytes;
+  size_t codes, sorted, order, counts, total, scan, sort, heavy_q, heavy_bound, heavy_state, bytes;
+  int64_t state_cap;
 };
 
-QueryLayout query_layout(int64_t m) {
+// `nearest`: also room for the walks heavy nearest queries hand over
+QueryLayout query_layout(int64_t m, bool nearest = false) {
   QueryLayout L{};
   const size_t mm = (size_t)m;
   size_t off = 0;
@@ -205,6 +208,9 @@ QueryLayout query_layout(int64_t m) {
   off = align_up(off + mm * 4, 256);
   L.heavy_bound = off;
   off = align_up(off + mm * 4, 256);
+  L.heavy_state = off;
+  L.state_cap = nearest ? heavy_state_cap(m) : 0;
+  off = align_up(off + (size_t)L.state_cap * kHeavyStateWords * 4, 256);
   L.bytes = off;
   return L;
 }
@@ -237,6 +243,7 @@ abx_status order_queries(const abx_bvh *b, const float *data, int64_t m, int wid
 // ---------------------------------------------------------------- internal enqueue sequences
 // Non-blocking pieces of the query entry points, shared with the server.
 size_t query_scratch_bytes(int64_t m) { return query_layout(m).bytes; }
+size_t nearest_scratch_bytes(int64_t m) { return query_layout(m, true).bytes; }
 
 // Spatial count phase: optional Morton ordering, counting traversal, scan of
 // the counts into offsets[0..m]; *d_total receives the device address of the
@@ -273,7 +280,7 @@ abx_status spatial_fill_enqueue(const abx_bvh *bvh, const abx_predicates *p, cha
 // Nearest queries: rows of min(k, n) entries; offsets optional.
 abx_status nearest_enqueue(const abx_bvh *bvh, const float *pts, int64_t m, int32_t k, int sort,
                            char *sc, int32_t *offsets, int32_t *indices, float *dist, hipStream_t s) {
-  const QueryLayout L = query_layout(m);
+  const QueryLayout L = query_layout(m, true);
   const int64_t kk = k < bvh->n ? k : bvh->n;
   if (offsets) ABX_TRY(row_offsets(offsets, m, (int32_t)kk, s));
   if (m == 0 || kk == 0) return ABX_OK;
@@ -282,7 +289,8 @@ abx_status nearest_enqueue(const abx_bvh *bvh, const float *pts, int64_t m, int3
   return launch_nearest(bvh, pts, m, order, (int)kk, indices, dist, nullptr,
                         reinterpret_cast<int32_t *>(sc + L.heavy_q),
                         reinterpret_cast<float *>(sc + L.heavy_bound),
-                        reinterpret_cast<uint32_t *>(sc + L.total), nearest_budget(), s);
+                        reinterpret_cast<uint32_t *>(sc + L.total),
+                        reinterpret_cast<int32_t *>(sc + L.heavy_state), L.state_cap, nearest_budget(), s);
 }
 
 abx_status hip_fail(hipError_t e) {
@@ -638,7 +646,7 @@ abx_status abx_query_nearest_sizes(const abx_bvh *bvh, int64_t m, int32_t k, siz
   ABX_TRY(check_bvh(bvh));
   if (m < 0 || k < 0 || !scratch_bytes) return ABX_ERR_INVALID_ARG;
   if (m >= kMaxCount) return ABX_ERR_OVERFLOW;
-  *scratch_bytes = query_layout(m).bytes;
+  *scratch_bytes = query_layout(m, true).bytes;
   return ABX_OK;
 }
 
@@ -650,7 +658,7 @@ static abx_status nearest_common(const abx_bvh *bvh, const float *points, int64_
   if (m < 0 || k < 0) return ABX_ERR_INVALID_ARG;
   if (m >= kMaxCount) return ABX_ERR_OVERFLOW;
   if (m > 0 && !points) return ABX_ERR_INVALID_ARG;
-  const QueryLayout L = query_layout(m);
+  const QueryLayout L = query_layout(m, true);
   if (!scratch || scratch_bytes < L.bytes || (reinterpret_cast<uintptr_t>(scratch) & 255))
     return ABX_ERR_INVALID_ARG;
   const int64_t kk = k < bvh->n ? k : bvh->n;
@@ -667,7 +675,8 @@ static abx_status nearest_common(const abx_bvh *bvh, const float *points, int64_
   return launch_nearest(bvh, points, m, order, (int)kk, indices, distances, stats,
                         reinterpret_cast<int32_t *>(sc + L.heavy_q),
                         reinterpret_cast<float *>(sc + L.heavy_bound),
-                        reinterpret_cast<uint32_t *>(sc + L.total), nearest_budget(), s);
+                        reinterpret_cast<uint32_t *>(sc + L.total),
+                        reinterpret_cast<int32_t *>(sc + L.heavy_state), L.state_cap, nearest_budget(), s);
 }
 
 abx_status abx_query_nearest(const abx_bvh *bvh, const float *points, int64_t m, int32_t k,

@@ -60,6 +60,21 @@ static_assert(sizeof(NodeQ16) == 32, "q16 node is 32 B");
 
 constexpr int kQ16Max = 65535;
 
+// Walk state a nearest query takes from the one-lane pass to the cooperative
+// pass (int32 words per saved query): entry count (-1: restart from the
+// root), pad, up to 64 (node, box distance) pairs (the next node and the
+// lane's stack of unexplored subtrees), then the candidate list (64 keys of
+// 64 bits).  A batch of m queries keeps the walks of its first
+// min(m / 8 + 1, kMaxSavedHeavy) heavy queries; later ones, and walks with a
+// deeper stack, restart from the root.
+constexpr int kHeavyStateEntries = 64;
+constexpr int kHeavyStateWords = 2 + 2 * kHeavyStateEntries + 2 * 64;
+constexpr int64_t kMaxSavedHeavy = 65536;
+inline int64_t heavy_state_cap(int64_t m) {
+  const int64_t c = m / 8 + 1;
+  return c < kMaxSavedHeavy ? c : kMaxSavedHeavy;
+}
+
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------------------

@@ -33,6 +33,7 @@
 
 namespace abx {
 size_t query_scratch_bytes(int64_t m);
+size_t nearest_scratch_bytes(int64_t m);
 abx_status spatial_count_enqueue(const abx_bvh *bvh, const abx_predicates *p, char *sc,
                                  int32_t *offsets, int64_t **d_total, hipStream_t s);
 abx_status spatial_fill_enqueue(const abx_bvh *bvh, const abx_predicates *p, char *sc,
@@ -159,9 +160,13 @@ struct abx_server {
 
 namespace {
 
+size_t request_scratch_bytes(const Req *q) {
+  return q->r.kind == ABX_REQ_NEAREST ? nearest_scratch_bytes(q->r.m) : query_scratch_bytes(q->r.m);
+}
+
 size_t dev_bytes_a(const abx_server *S, const Req *q) {
   const int64_t m = q->r.m;
-  size_t b = align_up((size_t)m * 12, kGrain) + align_up(query_scratch_bytes(m), kGrain);
+  size_t b = align_up((size_t)m * 12, kGrain) + align_up(request_scratch_bytes(q), kGrain);
   if (q->r.kind == ABX_REQ_NEAREST) b += 2 * align_up((size_t)(m * q->kk) * 4, kGrain);
   else b += align_up((size_t)(m + 1) * 4, kGrain);
   (void)S;
@@ -235,7 +240,7 @@ abx_status launch_a(abx_server *S, Req *q) {
   q->d_q = reinterpret_cast<float *>(d);
   d += align_up((size_t)m * 12, kGrain);
   q->d_scratch = d;
-  d += align_up(query_scratch_bytes(m), kGrain);
+  d += align_up(request_scratch_bytes(q), kGrain);
   q->h_off = reinterpret_cast<int32_t *>(h);
   h += align_up((size_t)(m + 1) * 4, kGrain);
   q->h_total = reinterpret_cast<int64_t *>(h);

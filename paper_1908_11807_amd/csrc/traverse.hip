@@ -472,6 +472,8 @@ struct NearestScratch {
   float *heavy_bound;
   uint32_t *counters;  // [0] heavy count, [1] next heavy query
   int64_t budget;
+  int32_t *heavy_state;  // saved walks (kHeavyStateWords each), or null
+  uint32_t state_cap;
 };
 
 int device_cus() {
@@ -491,7 +493,7 @@ abx_status nearest_k(const abx_bvh *b, const float *pts, int64_t m, const int32_
                      hipStream_t s) {
   const TreeArgs t = tree_args(b);
   const PlainMap map{k};
-  const HeavyList heavy{ns.heavy_q, ns.heavy_bound, ns.counters};
+  const HeavyList heavy{ns.heavy_q, ns.heavy_bound, ns.counters, ns.heavy_state, ns.state_cap};
   const unsigned g = grid_for(m, kTravBlock);
   if (stats)
     return launch("nearest_stats", s, [&] {
@@ -563,7 +565,8 @@ int64_t effective_budget(int64_t budget, int64_t m) {
 
 abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const int32_t *order,
                           int k, int32_t *idx, float *dist, int32_t *stats, int32_t *heavy_q,
-                          float *heavy_bound, uint32_t *counters, int64_t budget, hipStream_t s) {
+                          float *heavy_bound, uint32_t *counters, int32_t *heavy_state,
+                          int64_t state_cap, int64_t budget, hipStream_t s) {
   if (m == 0 || k == 0) return ABX_OK;
   if (k > kMaxHeapK) return ABX_ERR_UNSUPPORTED;
   if (k > kMaxRegK) {
@@ -576,7 +579,8 @@ abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const i
       return nearest_heap<ABX_PRIM_BOXES, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, s);
     return nearest_heap<ABX_PRIM_BOXES, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, s);
   }
-  const NearestScratch ns{heavy_q, heavy_bound, counters, effective_budget(budget, m)};
+  const NearestScratch ns{heavy_q, heavy_bound, counters, effective_budget(budget, m), heavy_state,
+                          (uint32_t)std::min<int64_t>(state_cap, kMaxSavedHeavy)};
   if (b->kind == ABX_PRIM_POINTS) {
     if (b->format == ABX_NODES_FP32)
       return nearest_fmt<ABX_PRIM_POINTS, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, ns, s);

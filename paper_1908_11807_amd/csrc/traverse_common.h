@@ -417,7 +417,10 @@ struct HeavyList {
   int32_t *q;          // caller's query index
   float *bound;        // k-th distance reached before the hand-off
   uint32_t *count;     // [0] entries, [1] next entry to serve
+  int32_t *state = nullptr;  // saved walks, kHeavyStateWords words each (optional)
+  uint32_t state_cap = 0;    // entries below this keep their walk
 };
+static_assert(kHeavyStateWords == 2 + 2 * kHeavyStateEntries + 2 * kMaxRegK, "saved walk layout");
 
 // Pass 1 for one query (one lane).  A walk that exceeds `budget` node
 // visits stops and hands the query to the cooperative pass with the k-th
@@ -463,16 +466,42 @@ __device__ __forceinline__ void nearest_lane(const TreeArgs &t, const Map &map,
       }
     }
     pend.flush_all(L);
+    if (!STATS && !done) {
+      const uint32_t h = atomicAdd(heavy.count, 1u);
+      heavy.q[h] = (int32_t)qi;
+      heavy.bound[h] = L.kth();
+      // the walk so far: the next node (not yet visited), the unexplored
+      // subtrees on the stack, the candidates; the workgroup resumes it.
+      // Lists of more than 32 keys restart instead: the save code's
+      // registers made their walk spill (48 keys: 9 -> 525 spill accesses).
+      if (K <= 32 && heavy.state && h < heavy.state_cap) {
+        int32_t *st = heavy.state + (int64_t)h * kHeavyStateWords;
+        if (sp + 1 > kHeavyStateEntries) {
+          st[0] = -1;  // too deep to save: the workgroup restarts from the root
+        } else {
+          st[2] = node;
+          st[3] = __float_as_int(0.0f);
+          int c = 1;
+          while (sp > 0) {
+            int32_t en;
+            float ed;
+            stack_pop2<kLdsDepthNearest, B>(lds_n, lds_d, ovf_n, ovf_d, sp, nl, en, ed);
+            st[2 + 2 * c] = en;
+            st[3 + 2 * c] = __float_as_int(ed);
+            ++c;
+          }
+          st[0] = c;
+          int64_t *keys = reinterpret_cast<int64_t *>(st + 2 + 2 * kHeavyStateEntries);
+#pragma unroll
+          for (int j = 0; j < K; ++j) keys[j] = L.key[j];
+        }
+      }
+      return;
+    }
   }
   if (STATS) {
     stats[2 * qi] = visited;
     stats[2 * qi + 1] = reads;
-    return;
-  }
-  if (!done) {
-    const uint32_t h = atomicAdd(heavy.count, 1u);
-    heavy.q[h] = (int32_t)qi;
-    heavy.bound[h] = L.kth();
     return;
   }
   knn_write<K>(L, info.kk, info.base, indices + info.out, dist + info.out);
@@ -518,6 +547,7 @@ __global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
     TreeArgs t, Map map, const float *__restrict__ pts, int32_t *__restrict__ indices,
     float *__restrict__ dist, HeavyList heavy) {
   using S = CoopShape<W>;
+  static_assert(kHeavyStateEntries < S::kFront, "a saved walk fits the first frontier");
   // two frontier buffers; during the depth-first phase the one not holding
   // the final frontier is the threads' stack window
   __shared__ int32_t s_fn[2][S::kCap];
@@ -541,15 +571,43 @@ __global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
     const KnnQuery q{pts[3 * (int64_t)qi], pts[3 * (int64_t)qi + 1], pts[3 * (int64_t)qi + 2]};
     KnnList<K> L;
     L.init(k);
-    if (tid == 0) {
+    // start from the walk the lane saved (its unexplored subtrees, and its
+    // candidates in thread 0's list), else from the root
+    int fsize = 1;
+    // (lists of more than 32 keys never save their walk)
+    const int32_t *st = K <= 32 && heavy.state && h < heavy.state_cap
+                            ? heavy.state + (int64_t)h * kHeavyStateWords
+                            : nullptr;
+    int c = st ? min(st[0], kHeavyStateEntries) : -1;
+    {
+      // every saved node must be an internal node, else restart from the root
+      bool bad = false;
+      for (int e = tid; e < c; e += S::kThreads) {
+        const int32_t nd = st[2 + 2 * e];
+        bad |= nd < 0 || nd >= t.n - 1;
+      }
+      if (__syncthreads_or(bad)) c = -1;
+    }
+    if (c >= 1) {
+      for (int e = tid; e < c; e += S::kThreads) {
+        s_fn[0][e] = st[2 + 2 * e];
+        s_fd[0][e] = __int_as_float(st[3 + 2 * e]);
+      }
+      fsize = c;
+      if (tid == 0) {
+        const int64_t *keys = reinterpret_cast<const int64_t *>(st + 2 + 2 * kHeavyStateEntries);
+#pragma unroll
+        for (int j = 0; j < K; ++j) L.key[j] = keys[j];
+      }
+    } else if (tid == 0) {
       s_fn[0][0] = info.root;
       s_fd[0][0] = 0.0f;
-      s_bound = __float_as_uint(heavy.bound[h]);
     }
+    if (tid == 0) s_bound = __float_as_uint(heavy.bound[h]);
     __syncthreads();
 
     // breadth-first expansion of the frontier
-    int cur = 0, fsize = 1;
+    int cur = 0;
     while (fsize > 0 && fsize < S::kFront) {
       // the size of the next frontier counts into s_size[cur ^ 1], last read
       // before the previous level's closing barrier
