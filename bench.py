@@ -106,9 +106,8 @@ def build_bytes_per_prim(node_format, morton_bits, kind_width=3, hierarchy="karr
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(each GPU would hold its own share; see the sharding notes). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (each GPU would "
+              "hold its own share of the queries). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

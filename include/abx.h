@@ -52,7 +52,7 @@ typedef enum {
   ABX_ERR_CAPACITY = 3,      /* result buffer too small; see query_spatial */
   ABX_ERR_OVERFLOW = 4,      /* a size or result count reaches 2^31        */
   ABX_ERR_HIP = 5,           /* a HIP runtime call failed                  */
-  ABX_ERR_UNSUPPORTED = 6,   /* valid request this build does not handle   */
+  ABX_ERR_UNSUPPORTED = 6,   /* valid request the library does not handle  */
   ABX_PENDING = 7            /* (server) the request has not completed yet */
 } abx_status;
 
