@@ -98,8 +98,9 @@ def build_bytes_per_prim(node_format, morton_bits, kind_width=3, hierarchy="karr
         b += 64 + 32                             # quantise: read FP32 node, write Q16 node
         if hierarchy == "karras":
             b += 4 + 8                           # depth-first order: parent link, first word
-            b += 7 * (8 + 8 + 8)                 # 7 pointer-jumping rounds: own, ancestor's, out
-            b += 8 + 4                           # quantise: the node's word and range end
+            b += 6 * (8 + 8 + 8)                 # 6 pointer-jumping rounds: own, ancestor's, out
+            b += 8 + 8 + 4 + 4                   # last round: words, range end, the index
+            b += 4 + 8                           # quantise: its own and its children's index
     return b
 
 

@@ -32,10 +32,9 @@ abx_status launch_agglo(bool wide, int kind, bool q16, const void *keys, const f
                         int32_t *range_hi, uint32_t *flags, TreeHeader *hdr, void *q16_leaves,
                         int32_t *frontier, uint32_t *frontier_count, hipStream_t s);
 abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, TreeHeader *hdr,
-                           const uint64_t *pre_w, const int32_t *other_end, NodeQ16 *dst,
-                           hipStream_t s);
-abx_status launch_preorder(const int32_t *parent_int, int64_t ni, uint64_t *work,
-                           const uint64_t **result, hipStream_t s);
+                           const int32_t *pre, NodeQ16 *dst, hipStream_t s);
+abx_status launch_preorder(const int32_t *parent_int, const int32_t *other_end, int64_t ni,
+                           uint64_t *work, int32_t *pre, hipStream_t s);
 // traverse.hip
 abx_status launch_query_codes(const abx_bvh *b, const float *q, int64_t m, int width,
                               uint32_t *codes, hipStream_t s);
@@ -171,8 +170,8 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   off = align_up(off + 256 + refit_frontier_cap(L.n) * 4, 256);
   L.staging = off;
   off = align_up(off + (L.q16 ? (size_t)L.ni * sizeof(NodeF32) : 0), 256);
-  L.pre = off;  // depth-first order: two buffers of 64-bit pointer-jumping words
-  off = align_up(off + (L.preorder ? 2 * (size_t)L.ni * 8 : 0), 256);
+  L.pre = off;  // depth-first order: two buffers of 64-bit pointer-jumping words, the index
+  off = align_up(off + (L.preorder ? 2 * (size_t)L.ni * 8 + (size_t)L.ni * 4 : 0), 256);
   L.sort = off;
   off = align_up(off + radix_sort_scratch_bytes(L.n, 3 * L.bits), 256);
   L.scratch_total = off;
@@ -422,7 +421,7 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
                            parent_leaf, parent_int, flags, hdr, tree + L.leaves_off, frontier,
                            fcount, s));
     }
-    const uint64_t *pre_w = nullptr;
+    int32_t *pre = nullptr;
     if (!agglo) {
       ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, fnodes, parent_leaf, parent_int, other_end,
                             flags, s));
@@ -431,11 +430,14 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
       // depth-first order of the Q16 nodes (written by the quantisation);
       // run beside the refit on a second stream it saved 0.04 ms of 0.4 at
       // 1e7 (the two share the GPU), so it stays on the caller's stream
-      if (L.preorder)
-        ABX_TRY(launch_preorder(parent_int, L.ni, reinterpret_cast<uint64_t *>(sc + L.pre), &pre_w, s));
+      if (L.preorder) {
+        uint64_t *work = reinterpret_cast<uint64_t *>(sc + L.pre);
+        pre = reinterpret_cast<int32_t *>(work + 2 * L.ni);
+        ABX_TRY(launch_preorder(parent_int, other_end, L.ni, work, pre, s));
+      }
     }
     if (L.q16)
-      ABX_TRY(launch_quantise(kind, fnodes, L.ni, hdr, pre_w, other_end,
+      ABX_TRY(launch_quantise(kind, fnodes, L.ni, hdr, pre,
                               reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
   }
   TreeHeader h;

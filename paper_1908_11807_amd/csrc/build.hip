@@ -682,32 +682,18 @@ __device__ __forceinline__ uint32_t q_hi(float x, float o, float s, float inv) {
 // boxes; in a point tree a leaf child's 12-byte slot holds the point's
 // float32 x, y, z instead (the traversal tells the two apart by the sign of
 // the reference), so point leaves need no second memory access.
-// depth-first index of node x from its finished pointer-jumping word (see
-// k_pre_*): first leaf of its range + left turns; -1 if x is out of range or
-// its path was longer than the rounds cover
-__device__ __forceinline__ int64_t pre_index(const uint64_t *__restrict__ w,
-                                             const int32_t *__restrict__ other_end, int64_t ni,
-                                             int64_t x) {
-  if (x < 0 || x >= ni) return -1;
-  const uint64_t v = w[x];
-  if ((int32_t)(uint32_t)v >= 0) return -1;
-  const int64_t j = other_end[x];
-  return (x < j ? x : j) + (int64_t)(v >> 32);
-}
-
 template <int KIND>
 __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restrict__ src,
                                                           int64_t ni, TreeHeader *__restrict__ hdr,
-                                                          const uint64_t *__restrict__ pre_w,
-                                                          const int32_t *__restrict__ other_end,
+                                                          const int32_t *__restrict__ pre,
                                                           NodeQ16 *__restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ni) return;
-  // with `pre_w`, node i goes to its depth-first slot and internal child
-  // references are renumbered the same way
+  // with `pre` (depth-first index, -1 if unknown), node i goes to slot
+  // pre[i] and internal child references are renumbered the same way
   int64_t slot = i;
-  if (pre_w) {
-    slot = pre_index(pre_w, other_end, ni, i);
+  if (pre) {
+    slot = pre[i];
     if (slot < 0 || slot >= ni) {
       atomicOr(&hdr->bad, 8);
       return;
@@ -741,13 +727,13 @@ __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restr
     }
   }
   int32_t ref[2] = {d.x, d.y};
-  if (pre_w) {
+  if (pre) {
 #pragma unroll
     for (int c = 0; c < 2; ++c)
       if (ref[c] >= 0) {
-        const int64_t r = pre_index(pre_w, other_end, ni, ref[c]);
+        const int32_t r = ref[c] < ni ? pre[ref[c]] : -1;
         if (r < 0 || r >= ni) atomicOr(&hdr->bad, 8);
-        ref[c] = (int32_t)r;
+        ref[c] = r;
       }
   }
   NodeQ16 out;
@@ -796,21 +782,41 @@ __global__ __launch_bounds__(kBuildBlock) void k_pre_jump(const uint64_t *__rest
   }
 }
 
-// scratch: 2 * ni words; returns (through *result) the buffer holding the
-// finished words, which k_quantise turns into depth-first indices
-abx_status launch_preorder(const int32_t *parent_int, int64_t ni, uint64_t *work,
-                           const uint64_t **result, hipStream_t s) {
-  *result = nullptr;
+// the last round: the finished count gives the index, first leaf of the
+// node's range + left turns (-1 if the path was longer than the rounds)
+__global__ __launch_bounds__(kBuildBlock) void k_pre_last(const uint64_t *__restrict__ in, int64_t ni,
+                                                          const int32_t *__restrict__ other_end,
+                                                          int32_t *__restrict__ pre) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ni) return;
+  const uint64_t x = in[i];
+  const int32_t a = (int32_t)(uint32_t)x;
+  uint64_t v = x >> 32;
+  int32_t rest = -1;
+  if (a >= 0 && a < ni) {
+    const uint64_t y = in[a];
+    v += y >> 32;
+    rest = (int32_t)(uint32_t)y;
+  }
+  const int64_t j = other_end[i];
+  pre[i] = rest >= 0 ? -1 : (int32_t)((i < j ? i : j) + (int64_t)v);
+}
+
+// scratch: 2 * ni words + ni int32 for the result
+abx_status launch_preorder(const int32_t *parent_int, const int32_t *other_end, int64_t ni,
+                           uint64_t *work, int32_t *pre, hipStream_t s) {
   if (ni <= 0) return ABX_OK;
   const unsigned g = grid_for(ni, kBuildBlock);
   uint64_t *buf[2] = {work, work + ni};
   ABX_TRY(launch("preorder", s, [&] { k_pre_init<<<g, kBuildBlock, 0, s>>>(parent_int, ni, buf[0]); }));
-  for (int r = 0; r < kPreRounds; ++r) {
+  for (int r = 0; r + 1 < kPreRounds; ++r) {
     const int a = r & 1, b = a ^ 1;
     ABX_TRY(launch("preorder", s, [&] { k_pre_jump<<<g, kBuildBlock, 0, s>>>(buf[a], ni, buf[b]); }));
   }
-  *result = buf[kPreRounds & 1];
-  return ABX_OK;
+  const int f = (kPreRounds - 1) & 1;
+  return launch("preorder", s, [&] {
+    k_pre_last<<<g, kBuildBlock, 0, s>>>(buf[f], ni, other_end, pre);
+  });
 }
 
 // ------------------------------------------------------------ host launchers
@@ -910,16 +916,15 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
 }
 
 abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, TreeHeader *hdr,
-                           const uint64_t *pre_w, const int32_t *other_end, NodeQ16 *dst,
-                           hipStream_t s) {
+                           const int32_t *pre, NodeQ16 *dst, hipStream_t s) {
   if (ni <= 0) return ABX_OK;
   const unsigned g = grid_for(ni, kBuildBlock);
   if (kind == ABX_PRIM_POINTS)
     return launch("quantise", s, [&] {
-      k_quantise<ABX_PRIM_POINTS><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, pre_w, other_end, dst);
+      k_quantise<ABX_PRIM_POINTS><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, pre, dst);
     });
   return launch("quantise", s, [&] {
-    k_quantise<ABX_PRIM_BOXES><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, pre_w, other_end, dst);
+    k_quantise<ABX_PRIM_BOXES><<<g, kBuildBlock, 0, s>>>(src, ni, hdr, pre, dst);
   });
 }
 

@@ -39,8 +39,7 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
                         TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
                         uint32_t *frontier_count, hipStream_t s);
 abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, TreeHeader *hdr,
-                           const uint64_t *pre_w, const int32_t *other_end, NodeQ16 *dst,
-                           hipStream_t s);
+                           const int32_t *pre, NodeQ16 *dst, hipStream_t s);
 size_t refit_frontier_cap(int64_t n);
 int max_tree_depth();
 bool graph_capturing();
@@ -254,7 +253,7 @@ abx_status abx_forest_build(const abx_forest_primitives *prims, void *tree_mem, 
                          reinterpret_cast<int32_t *>(sc + L.frontier + 256),
                          reinterpret_cast<uint32_t *>(sc + L.frontier), s));
     if (q16)
-      ABX_TRY(launch_quantise(ABX_PRIM_POINTS, fnodes, L.ni, hdr, nullptr, nullptr,
+      ABX_TRY(launch_quantise(ABX_PRIM_POINTS, fnodes, L.ni, hdr, nullptr,
                               reinterpret_cast<NodeQ16 *>(tree + L.nodes), s));
   }
   ABX_TRY(forest_launch_roots(offs, T, other_end, reinterpret_cast<const int32_t *>(tree + L.leaves),
