@@ -251,6 +251,24 @@ def main():
                           frac=round(rad_bytes / (rad_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
     }
 
+    # achievable HBM bandwidth: a plain 1 GiB device copy (reads and writes 1 GiB)
+    cx = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    cy = torch.empty_like(cx)
+    cms = []
+    for i in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        cy.copy_(cx)
+        b.record()
+        b.synchronize()
+        if i:
+            cms.append(a.elapsed_time(b))
+    copy_gbs = 2 * cx.numel() * 4 / (float(np.median(cms)) * 1e-3) / 1e9
+    del cx, cy
+    roof["copy_gbs"] = round(copy_gbs, 1)
+    if roof.get("achieved") is not None:
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+
     out = {
         "metric": "queries/s (kNN k=10, radius) + BVH build Mprims/s at 1e7 pts; p99 batch latency",
         "value": round(2 * m / (ms_step * 1e-3), 1),
@@ -465,7 +483,7 @@ def bench_serving(args, standalone):
         return reqs
 
     def run(reqs, t0, paced):
-        lat, done, live = [], 0, {}
+        lat, gpu_t, done, live = [], [], 0, {}
         qsum = 0
         last = t0
         for r in reqs:
@@ -476,6 +494,7 @@ def bench_serving(args, standalone):
                         res = srv.poll(tk, copy=False)
                         if res is not None:
                             lat.append(res["t_done"] - res["t_arrival"])
+                            gpu_t.append(res["t_device"])
                             last = max(last, res["t_done"])
                             srv.release(tk)
                             del live[tk]
@@ -489,24 +508,28 @@ def bench_serving(args, standalone):
         for tk in list(live):
             res = srv.wait(tk, copy=False)
             lat.append(res["t_done"] - res["t_arrival"])
+            gpu_t.append(res["t_device"])
             last = max(last, res["t_done"])
             srv.release(tk)
-        return np.array(lat), qsum, last - t0
+        return np.array(lat), np.array(gpu_t), qsum, last - t0
 
     nreq = max(args.serve_requests, 20)
     nwarm = min(nreq, 1000)
     run(make(nwarm, 700, 1.0), abx.server_now(), paced=False)   # warm-up
-    lat, qsum, span = run(make(nreq, 701, 1.0), abx.server_now(), paced=False)
+    lat, gpu_t, qsum, span = run(make(nreq, 701, 1.0), abx.server_now(), paced=False)
     sat_rps = nreq / span
     out = {"saturated_requests_per_s": round(sat_rps, 1), "saturated_queries_per_s": round(qsum / span, 1),
            "loads": []}
     for i, f in enumerate(float(x) for x in args.serve_loads.split(",")):
         reqs = make(nreq, 710 + i, f * sat_rps)
-        lat, qsum, span = run(reqs, abx.server_now() + 0.01, paced=True)
+        lat, gpu_t, qsum, span = run(reqs, abx.server_now() + 0.01, paced=True)
         out["loads"].append({"offered": f, "requests_per_s": round(nreq / span, 1),
                              "queries_per_s": round(qsum / span, 1),
                              "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
-                             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3)})
+                             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                             # the requests' own GPU time (copies + kernels, stream events)
+                             "device_p50_ms": round(1e3 * float(np.percentile(gpu_t, 50)), 3),
+                             "device_p99_ms": round(1e3 * float(np.percentile(gpu_t, 99)), 3)})
     st = srv.stats()
     out["server"] = {"slots": 4, "budget_bytes": budget, "max_in_flight": st["max_in_flight"],
                      "device_high_water": st["device_high_water"], "failed": st["failed"]}
@@ -541,10 +564,26 @@ def cpu_baseline(pts, q, r, k, budget_s):
         t_used += time.perf_counter() - a
         done += chunk
         chunk = min(chunk * 2, 256)
-    return {"value": round(2 * done / t_used, 2), "unit": "queries/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same oracle on one host thread, over the next queries of the sample
+    oracle.set_num_threads(1)
+    done1, t1, chunk = 0, 0.0, 2
+    try:
+        while t1 < budget_s / 4 and done + done1 + chunk <= sel.shape[0]:
+            qq = q[sel[done + done1:done + done1 + chunk]]
+            a = time.perf_counter()
+            oracle.spatial(pts, oracle.POINTS, qq, oracle.WITHIN, radius=r)
+            oracle.nearest(pts, oracle.POINTS, qq, k)
+            t1 += time.perf_counter() - a
+            done1 += chunk
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": round(2 * done / t_used, 2), "unit": "queries/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{done} seeded queries of the same workload, each answered by brute-force "
-                      f"radius and k={k} nearest over all {pts.shape[0]} points ({t_used:.1f} s)"}
+                      f"radius and k={k} nearest over all {pts.shape[0]} points ({t_used:.1f} s)",
+            "value_1thread": round(2 * done1 / t1, 2) if t1 > 0 else None,
+            "sample_1thread": f"{done1} further queries of the sample on one thread ({t1:.1f} s)"}
 
 
 if __name__ == "__main__":

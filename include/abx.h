@@ -418,6 +418,10 @@ typedef struct {
   const int32_t *indices;          /* HOST [total]                          */
   const float *distances;          /* HOST [total] (nearest) or NULL        */
   double t_arrival, t_admit, t_done;
+  double t_device;                 /* GPU time of the request's phases (s):
+                                      its copies and kernels, from events on
+                                      its stream; excludes queueing and the
+                                      wait for the fill's memory            */
 } abx_result;
 
 typedef struct {
@@ -430,7 +434,10 @@ typedef struct abx_server abx_server;
 abx_status abx_server_create(const abx_server_config *cfg, abx_server **out /*host*/);
 abx_status abx_server_add_tree(abx_server *srv, const abx_bvh *tree, int32_t *id /*host*/);
 /* Queues a copy of *req; returns at once.  ABX_ERR_CAPACITY is reported in
- * the result of a request whose reservation can never fit. */
+ * the result of a request whose reservation can never fit: at admission, one
+ * larger than an arena; at the fill, one whose result space does not fit
+ * while nothing else holds either arena.  A fill that waits for host space
+ * held by results not yet released waits for abx_server_release. */
 abx_status abx_server_submit(abx_server *srv, const abx_request *req, uint64_t *ticket /*host*/);
 /* ABX_PENDING until the request has completed (results host-visible). */
 abx_status abx_server_poll(abx_server *srv, uint64_t ticket, abx_result *out /*host*/);

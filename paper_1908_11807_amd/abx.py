@@ -92,7 +92,8 @@ class Request(C.Structure):
 class Result(C.Structure):
     _fields_ = [("status", C.c_int), ("m", C.c_int64), ("total", C.c_int64),
                 ("offsets", C.c_void_p), ("indices", C.c_void_p), ("distances", C.c_void_p),
-                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("t_device", C.c_double)]
 
 
 class ServerStats(C.Structure):
@@ -639,7 +640,7 @@ class Server:
     def _result(self, r, copy):
         import numpy as np
         out = dict(status=r.status, m=r.m, total=r.total, t_arrival=r.t_arrival,
-                   t_admit=r.t_admit, t_done=r.t_done)
+                   t_admit=r.t_admit, t_done=r.t_done, t_device=r.t_device)
         if r.status == OK and copy:
             def arr(ptr, n, ct, dt):
                 if not ptr or n == 0:

@@ -119,6 +119,7 @@ struct Req {
   int64_t kk = 0, total = 0;
   abx_status status = ABX_OK;
   double t_admit = 0, t_done = 0, sim_deadline = 0;
+  double t_device = 0;        // summed GPU time of the request's phases
   Block dev_a, dev_b, host;   // device: phase A / fill reservation; host: results
   // carved device pointers
   float *d_q = nullptr;
@@ -134,7 +135,8 @@ struct Req {
 
 struct Slot {
   hipStream_t s = nullptr;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr;        // completion (polled)
+  hipEvent_t t0 = nullptr, t1 = nullptr;  // timing: start and end of a phase
   Req *r = nullptr;
 };
 
@@ -259,6 +261,7 @@ abx_status launch_a(abx_server *S, Req *q) {
     q->sim_deadline = now_s() + 1e-9 * S->cfg.sim_ns_per_query * (double)(m > 0 ? m : 1);
     return ABX_OK;
   }
+  ABX_HIP(hipEventRecord(sl.t0, sl.s));
   if (m > 0) ABX_HIP(hipMemcpyAsync(q->d_q, q->r.queries, (size_t)m * 12, hipMemcpyHostToDevice, sl.s));
   if (q->r.kind == ABX_REQ_NEAREST) {
     ABX_TRY(nearest_enqueue(tree, q->d_q, m, q->r.k, sort_request(q), q->d_scratch, nullptr, q->d_idx,
@@ -273,6 +276,7 @@ abx_status launch_a(abx_server *S, Req *q) {
     ABX_TRY(spatial_count_enqueue(tree, &p, q->d_scratch, q->d_off, &q->d_total, sl.s));
     ABX_HIP(hipMemcpyAsync(q->h_total, q->d_total, 8, hipMemcpyDeviceToHost, sl.s));
   }
+  ABX_HIP(hipEventRecord(sl.t1, sl.s));
   ABX_HIP(hipEventRecord(sl.ev, sl.s));
   return ABX_OK;
 }
@@ -303,12 +307,17 @@ bool try_launch_b(abx_server *S, Req *q, abx_status *err) {
   Slot &sl = S->slots[q->slot];
   const abx_bvh *tree = S->trees[q->r.tree];
   abx_predicates p{ABX_PRED_WITHIN, q->d_q, m, nullptr, q->r.radius, sort_request(q)};
+  if (hipEventRecord(sl.t0, sl.s) != hipSuccess) {
+    *err = ABX_ERR_HIP;
+    return true;
+  }
   *err = spatial_fill_enqueue(tree, &p, q->d_scratch, q->d_off, q->d_idx, sl.s);
   if (*err == ABX_OK && hipMemcpyAsync(q->h_off, q->d_off, (size_t)(m + 1) * 4, hipMemcpyDeviceToHost, sl.s) != hipSuccess)
     *err = ABX_ERR_HIP;
   if (*err == ABX_OK && t > 0 &&
       hipMemcpyAsync(q->h_idx, q->d_idx, (size_t)t * 4, hipMemcpyDeviceToHost, sl.s) != hipSuccess)
     *err = ABX_ERR_HIP;
+  if (*err == ABX_OK && hipEventRecord(sl.t1, sl.s) != hipSuccess) *err = ABX_ERR_HIP;
   if (*err == ABX_OK && hipEventRecord(sl.ev, sl.s) != hipSuccess) *err = ABX_ERR_HIP;
   return true;
 }
@@ -332,8 +341,9 @@ bool step(abx_server *S) {
       if (try_launch_b(S, q, &err)) {
         changed = true;
         if (err != ABX_OK) finish(S, q, err);
-      } else if (S->dev.used() == q->dev_a.bytes) {
-        // alone on the device and the result space still does not fit
+      } else if (S->dev.used() == q->dev_a.bytes && S->host.used() == q->host.bytes) {
+        // alone in both arenas and the result space still does not fit (results
+        // that the caller has not released yet hold host space: wait for them)
         finish(S, q, ABX_ERR_CAPACITY);
         changed = true;
       } else {
@@ -346,6 +356,12 @@ bool step(abx_server *S) {
     if (!S->cfg.simulate && hipEventQuery(sl.ev) != hipSuccess) {
       finish(S, q, ABX_ERR_HIP);
       continue;
+    }
+    if (S->cfg.simulate) {
+      q->t_device += 1e-9 * S->cfg.sim_ns_per_query * (double)(q->r.m > 0 ? q->r.m : 1);
+    } else {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, sl.t0, sl.t1) == hipSuccess) q->t_device += 1e-3 * (double)ms;
     }
     if (q->phase == P_RUN_A && q->r.kind == ABX_REQ_RADIUS) {
       q->total = S->cfg.simulate ? 10 * q->r.m : *q->h_total;
@@ -448,6 +464,7 @@ void fill_result(const Req *q, abx_result *o) {
   o->t_arrival = q->r.t_arrival;
   o->t_admit = q->t_admit;
   o->t_done = q->t_done;
+  o->t_device = q->t_device;
 }
 
 }  // namespace
@@ -475,8 +492,11 @@ abx_status abx_server_create(const abx_server_config *cfg, abx_server **out) {
     S->slots.resize(cfg->slots);
     for (auto &sl : S->slots) {
       if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+          hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreate(&sl.t0) != hipSuccess || hipEventCreate(&sl.t1) != hipSuccess) {
         for (auto &x : S->slots) {
+          if (x.t0) (void)hipEventDestroy(x.t0);
+          if (x.t1) (void)hipEventDestroy(x.t1);
           if (x.ev) (void)hipEventDestroy(x.ev);
           if (x.s) (void)hipStreamDestroy(x.s);
         }
@@ -593,6 +613,8 @@ abx_status abx_server_destroy(abx_server *S) {
   for (auto &kv : S->reqs) delete kv.second;
   if (!S->cfg.simulate) {
     for (auto &sl : S->slots) {
+      if (sl.t0) (void)hipEventDestroy(sl.t0);
+      if (sl.t1) (void)hipEventDestroy(sl.t1);
       if (sl.ev) (void)hipEventDestroy(sl.ev);
       if (sl.s) (void)hipStreamDestroy(sl.s);
     }

@@ -66,6 +66,9 @@ def test_serving_results_alone_equal_mix(orc):
             assert np.array_equal(a["indices"], b["indices"])
             assert np.array_equal(a["distances"], b["distances"])
         assert a["t_arrival"] <= a["t_admit"] <= a["t_done"]
+        # the request's GPU time lies inside its admit-to-done span (event and
+        # host clocks differ by a little)
+        assert 0.0 <= a["t_device"] <= a["t_done"] - a["t_admit"] + 1e-3
     # oracle parity on every request (rows sampled in the larger ones)
     for r, b in zip(reqs, mix):
         p = prims[r["tree"]]

@@ -26,6 +26,8 @@ def test_fifo_admission_and_slot_limit():
     for r in res:
         assert r["t_arrival"] <= r["t_admit"] <= r["t_done"]
         assert r["t_done"] - r["t_admit"] >= 500 * 2000e-9 * 0.99
+        # one phase of the simulated executor's length
+        assert r["t_device"] == pytest.approx(500 * 2000e-9)
         assert r["offsets"].tolist() == list(range(0, 8 * 501, 8))
     for t in tickets:
         s.release(t)
@@ -69,6 +71,7 @@ def test_radius_two_phases_and_host_release_backpressure():
     for t in tickets:
         r = s.wait(t)
         assert r["status"] == abx.OK and r["total"] == 10 * 200
+        assert r["t_device"] == pytest.approx(2 * 200 * 100e-9)    # count and fill phases
         done.append(r)
         s.release(t)
     assert s.stats()["host_high_water"] <= 64 * 1024
