@@ -80,10 +80,11 @@ def algorithmic_bytes(stats, node_b, leaf_b, per_query_fixed):
     return int(per_query_fixed * s.shape[0] + node_b * s[:, 0].sum() + leaf_b * s[:, 1].sum())
 
 
-def build_bytes_per_prim(node_format, morton_bits, kind_width=3, hierarchy="karras"):
-    """Algorithmic bytes of one build, per point primitive (Karras hierarchy,
-    two-phase refit, 8-bit radix digits; Q16 Karras trees also renumber their
-    nodes depth-first)."""
+def build_bytes_per_prim(node_format, morton_bits, kind_width=3, depth_first=False):
+    """Algorithmic bytes of one build, per point primitive (chunked refit,
+    8-bit radix digits; `depth_first`: the tree's nodes were renumbered in
+    depth-first order, which Q16 Karras trees of 2^22 primitives and more
+    get by default)."""
     keyb = 8 if morton_bits > 10 else 4          # 63- or 30-bit Morton keys
     passes = 8 if morton_bits > 10 else 4        # 8-bit digits
     w = 4 * kind_width                           # 12 B point (24 B box)
@@ -96,7 +97,7 @@ def build_bytes_per_prim(node_format, morton_bits, kind_width=3, hierarchy="karr
     b += 4 + 4 + 64 + 28                         # refit, node: parent, range end, node, sibling
     if node_format == "q16":
         b += 64 + 32                             # quantise: read FP32 node, write Q16 node
-        if hierarchy == "karras":
+        if depth_first:
             b += 4 + 8                           # depth-first order: parent link, first word
             b += 6 * (8 + 8 + 8)                 # 6 pointer-jumping rounds: own, ancestor's, out
             b += 8 + 8 + 4 + 4                   # last round: words, range end, the index
@@ -240,7 +241,8 @@ def main():
                      speedup_vs_2p=round(rad_ms / float(np.median(t1p)), 3))
 
     # the other two phases against the same HBM peak (algorithmic bytes)
-    bpp = build_bytes_per_prim(args.nodes, args.morton_bits, hierarchy=args.hierarchy)
+    bpp = build_bytes_per_prim(args.nodes, args.morton_bits,
+                               depth_first=int(t.layout.node_order) == abx.ORDER_DEPTH_FIRST)
     rad_bytes = alg["spatial_count"] + alg["spatial_fill"]
     phase_rooflines = {
         "build": dict(bytes_per_prim=bpp, achieved=round(bpp * n / (build_ms * 1e-3) / 1e9, 1),

@@ -1,0 +1,94 @@
+"""Host logic of bench.py, without a GPU: the one-GPU guard, the algorithmic
+byte counts behind the roofline figures, the lookup of committed HBM
+traffic records (and their invalidation when the kernel sources change),
+and the shape of the CPU-oracle baseline."""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_algorithmic_bytes_counts_visits_and_reads():
+    # rows: (internal nodes visited, leaf records read) per query
+    stats = np.array([[3, 0], [10, 2], [0, 0]], np.int32)
+    got = bench.algorithmic_bytes(stats, node_b=32, leaf_b=32, per_query_fixed=96)
+    # 3 queries x 96 + 13 visits x 32 + 2 reads x 32, counted by hand
+    assert got == 288 + 416 + 64
+
+
+def test_build_bytes_differences():
+    fp32 = bench.build_bytes_per_prim("fp32", 21)
+    q16 = bench.build_bytes_per_prim("q16", 21)
+    q16_df = bench.build_bytes_per_prim("q16", 21, depth_first=True)
+    # quantisation reads a 64-byte node and writes a 32-byte one
+    assert q16 - fp32 == 64 + 32
+    # the depth-first renumbering is charged only when it ran
+    assert q16_df > q16
+    # 30-bit keys: half the key bytes and half the sort passes
+    assert bench.build_bytes_per_prim("fp32", 10) < fp32
+    # box primitives read 24 bytes where points read 12, three times (scene,
+    # Morton, refit gather)
+    assert bench.build_bytes_per_prim("fp32", 21, kind_width=6) - fp32 == 3 * 12
+
+
+def test_committed_traffic_records_match_the_sources():
+    for nodes in ("q16", "fp32"):
+        path = os.path.join(ROOT, "profiles", f"traffic_nearest_c3_{nodes}.json")
+        if not os.path.exists(path):
+            pytest.skip(f"no traffic record for {nodes}")
+        rec = json.load(open(path))
+        traffic, src = bench.measured_traffic("nearest+coop", "C3", nodes, 10)
+        assert src == os.path.relpath(path, ROOT)
+        assert traffic == rec["traffic_bytes_per_launch"]
+        # the figure is the copy-calibrated counters, as recorded
+        kib = sum(rec["fetch_kib_per_launch"].values()) * rec["fetch_scale"] + \
+            sum(rec["write_kib_per_launch"].values()) * rec["write_scale"]
+        assert abs(traffic - 1024 * kib) <= 1
+    assert bench.measured_traffic("nearest+coop", "C3", "q16", 11) == (None, None)
+
+
+def test_traffic_record_is_dropped_when_sources_change(tmp_path, monkeypatch):
+    src = os.path.join(ROOT, "profiles", "traffic_nearest_c3_q16.json")
+    if not os.path.exists(src):
+        pytest.skip("no traffic record")
+    rec = json.load(open(src))
+    (tmp_path / "profiles").mkdir()
+    shutil.copy(src, tmp_path / "profiles" / "traffic_nearest_c3_q16.json")
+    for s in rec["sources"]:
+        dst = tmp_path / s
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        shutil.copy(os.path.join(ROOT, s), dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("nearest+coop", "C3", "q16", 10)[0] == rec["traffic_bytes_per_launch"]
+    with open(tmp_path / rec["sources"][0], "a") as f:
+        f.write("\n// edited\n")
+    assert bench.measured_traffic("nearest+coop", "C3", "q16", 10) == (None, None)
+
+
+def test_cpu_baseline_reports_the_oracle_rate():
+    from paper_1908_11807_amd import datagen
+    pts = datagen.uniform_cube(20000, 1)
+    q = datagen.uniform_cube(4000, 2)
+    out = bench.cpu_baseline(pts, q, 0.04, 10, 0.5)
+    assert out["kind"] == "oracle" and out["unit"] == "queries/s"
+    assert out["value"] > 0 and out["cores"] >= 1
+    assert out["value_1thread"] is not None and out["value_1thread"] > 0
+    import oracle
+    # the thread count is restored after the one-thread sample
+    assert oracle.num_threads() == out["cores"]
