@@ -427,6 +427,9 @@ typedef struct {
 typedef struct {
   int64_t submitted, completed, failed, queries, max_in_flight, in_flight, queued;
   size_t device_high_water, host_high_water;
+  int64_t requeued;        /* radius requests sent back to the queue head after
+                              their count: fills that waited on each other's
+                              reservations (the earliest keeps its slot)   */
 } abx_server_stats;
 
 typedef struct abx_server abx_server;

@@ -100,7 +100,7 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("queries", C.c_int64), ("max_in_flight", C.c_int64), ("in_flight", C.c_int64),
                 ("queued", C.c_int64), ("device_high_water", C.c_size_t),
-                ("host_high_water", C.c_size_t)]
+                ("host_high_water", C.c_size_t), ("requeued", C.c_int64)]
 
 
 REQ_RADIUS, REQ_NEAREST = 0, 1

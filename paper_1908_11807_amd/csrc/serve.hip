@@ -28,6 +28,7 @@
 #include <thread>
 #include <unordered_map>
 #include <vector>
+#include <vector>
 
 #include "abx_internal.h"
 
@@ -381,6 +382,43 @@ bool step(abx_server *S) {
     }
     if (q->r.kind == ABX_REQ_NEAREST) nearest_offsets(q);
     finish(S, q, ABX_OK);
+  }
+  // 1b. fills that wait on each other: when every occupied slot holds a fill
+  // waiting for memory, no running phase will free any, and each may be
+  // blocked by the others' reservations.  The earliest request keeps its
+  // slot; the later ones give their reservations back and return to the
+  // head of the queue (to be counted again once the earliest has finished).
+  if (fill_waiting) {
+    Req *keep = nullptr;
+    bool running = false;
+    for (auto &sl : S->slots) {
+      if (!sl.r) continue;
+      if (sl.r->phase != P_WAIT_FILL) {
+        running = true;
+      } else if (!keep || sl.r->ticket < keep->ticket) {
+        keep = sl.r;
+      }
+    }
+    if (!running && keep) {
+      std::vector<Req *> back;
+      for (auto &sl : S->slots) {
+        Req *q = sl.r;
+        if (!q || q == keep) continue;
+        release_block(S->dev, q->dev_a);
+        release_block(S->dev, q->dev_b);
+        release_block(S->host, q->host);
+        q->phase = P_QUEUED;
+        q->slot = -1;
+        q->total = 0;
+        sl.r = nullptr;
+        S->in_flight--;
+        S->st.requeued++;
+        back.push_back(q);
+      }
+      std::sort(back.begin(), back.end(), [](const Req *a, const Req *b) { return a->ticket > b->ticket; });
+      for (Req *q : back) S->queue.push_front(q);
+      if (!back.empty()) changed = true;
+    }
   }
   // 2. admission: FIFO, stop while a fill waits for memory (it drains the device)
   while (!fill_waiting && !S->queue.empty()) {

@@ -96,3 +96,28 @@ def test_submit_validation():
     with pytest.raises(abx.AbxError):
         s.submit(0, abx.REQ_NEAREST, np.zeros((3, 3), np.float32), k=129)  # k > 128
     s.close()
+
+
+def test_fills_waiting_on_each_other_are_serialised():
+    # A radius request of m = 1000 reserves ~58 KB for its count and then
+    # 40 KB for its 10 000 simulated results.  Two counts fit the budget
+    # together, but then neither fill fits beside the other's reservation:
+    # the later request gives its reservation back and runs after the first.
+    budget = 2 * 58_000 + 20_000
+    s = _server(slots=4, budget_bytes=budget, host_bytes=1 << 26, sim_ns_per_query=100)
+    q = np.zeros((1000, 3), np.float32)
+    tickets = [s.submit(0, abx.REQ_RADIUS, q, radius=0.1) for _ in range(3)]
+    deadline = abx.server_now() + 10.0
+    res = {}
+    while len(res) < len(tickets) and abx.server_now() < deadline:
+        for t in tickets:
+            if t not in res:
+                r = s.poll(t)
+                if r is not None:
+                    res[t] = r
+    assert len(res) == len(tickets), s.stats()          # no request is stuck
+    for t in tickets:
+        assert res[t]["status"] == abx.OK and res[t]["total"] == 10 * 1000
+    st = s.stats()
+    assert st["requeued"] >= 1 and st["device_high_water"] <= budget
+    s.close()
