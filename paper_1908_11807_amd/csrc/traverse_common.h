@@ -518,6 +518,11 @@ __device__ __forceinline__ float wave_min(float v) {
 // more registers than a 1024-thread workgroup leaves per lane
 constexpr int coop_waves(int K) { return K > 16 ? 8 : 16; }
 
+// the depth-first phase shares the workgroup's bound every 2^kCoopShareLog2
+// steps: a fresher bound prunes more, sharing costs a wave-wide minimum and
+// an LDS atomic per wave
+constexpr int kCoopShareLog2 = 3;
+
 // Pass 2: a workgroup of W wavefronts per heavy query.  The launch lasts as
 // long as its heaviest query, whose walk is split W*64 ways.  The workgroup
 // expands the tree breadth-first until the frontier holds 256*W nodes, then
@@ -674,10 +679,12 @@ __global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
     KnnPending pend;
     pend.init();
     for (int64_t it = 0; it < 4 * t.n + 64; ++it) {
-      // share the workgroup's bound: one LDS atomic per wave and step
-      const float wm = wave_min(fminf(bound, L.kth()));
-      if (lane == 0) lds_min(&s_bound, wm);
-      bound = fminf(wm, __uint_as_float(s_bound));
+      // share the workgroup's bound (each lane also prunes with its own list)
+      if ((it & ((1 << kCoopShareLog2) - 1)) == 0) {
+        const float wm = wave_min(fminf(bound, L.kth()));
+        if (lane == 0) lds_min(&s_bound, wm);
+        bound = fminf(wm, __uint_as_float(s_bound));
+      }
       if (!__any(active)) break;
       if (active) {
         if (node < 0)
