@@ -28,7 +28,6 @@
 #include <thread>
 #include <unordered_map>
 #include <vector>
-#include <vector>
 
 #include "abx_internal.h"
 
