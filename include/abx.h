@@ -253,7 +253,7 @@ abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, 
  * exactly), starting from the bound the lane had reached.  Results do not
  * depend on the value.  (k > 64 is walked by one lane throughout.)
  * abx_set_nearest_budget sets the process-wide budget (<= 0: unlimited, i.e.
- * one lane per query throughout) and returns the previous one.  Default 24576.
+ * one lane per query throughout) and returns the previous one.  Default 22528.
  * A batch of m queries uses min(budget, max(512, m / 24)): small batches
  * leave the GPU idle and hand heavy queries to whole workgroups sooner. */
 int64_t abx_set_nearest_budget(int64_t visits);

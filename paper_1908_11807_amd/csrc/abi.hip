@@ -53,7 +53,7 @@ int max_tree_depth();
 
 // node visits after which a nearest query leaves the one-lane pass for the
 // cooperative pass (abx_set_nearest_budget)
-std::atomic<int64_t> g_nearest_budget{24576};
+std::atomic<int64_t> g_nearest_budget{22528};
 int64_t nearest_budget() { return g_nearest_budget.load(std::memory_order_relaxed); }
 
 namespace {

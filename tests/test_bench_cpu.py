@@ -4,7 +4,6 @@ traffic records (and their invalidation when the kernel sources change),
 and the shape of the CPU-oracle baseline."""
 import json
 import os
-import shutil
 import subprocess
 import sys
 
@@ -47,13 +46,27 @@ def test_build_bytes_differences():
     assert bench.build_bytes_per_prim("fp32", 21, kind_width=6) - fp32 == 3 * 12
 
 
-def test_committed_traffic_records_match_the_sources():
+def _sources_hash(root, sources):
+    import hashlib
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(root, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def test_committed_traffic_records():
+    # a record is used while the kernel sources hash to its value, and
+    # ignored once they have changed (the counters must then be taken again)
     for nodes in ("q16", "fp32"):
         path = os.path.join(ROOT, "profiles", f"traffic_nearest_c3_{nodes}.json")
         if not os.path.exists(path):
             pytest.skip(f"no traffic record for {nodes}")
         rec = json.load(open(path))
         traffic, src = bench.measured_traffic("nearest+coop", "C3", nodes, 10)
+        if _sources_hash(ROOT, rec["sources"]) != rec["sources_sha256"]:
+            assert (traffic, src) == (None, None)
+            continue
         assert src == os.path.relpath(path, ROOT)
         assert traffic == rec["traffic_bytes_per_launch"]
         # the figure is the copy-calibrated counters, as recorded
@@ -64,20 +77,21 @@ def test_committed_traffic_records_match_the_sources():
 
 
 def test_traffic_record_is_dropped_when_sources_change(tmp_path, monkeypatch):
-    src = os.path.join(ROOT, "profiles", "traffic_nearest_c3_q16.json")
-    if not os.path.exists(src):
-        pytest.skip("no traffic record")
-    rec = json.load(open(src))
+    sources = ["src/a.hip", "src/b.h"]
+    for i, s in enumerate(sources):
+        (tmp_path / s).parent.mkdir(parents=True, exist_ok=True)
+        (tmp_path / s).write_text(f"// kernel source {i}\n")
+    rec = {"kernel": "nearest+coop", "workload": "C3", "nodes": "q16", "k": 10,
+           "sources": sources, "sources_sha256": _sources_hash(str(tmp_path), sources),
+           "traffic_bytes_per_launch": 123456789}
     (tmp_path / "profiles").mkdir()
-    shutil.copy(src, tmp_path / "profiles" / "traffic_nearest_c3_q16.json")
-    for s in rec["sources"]:
-        dst = tmp_path / s
-        dst.parent.mkdir(parents=True, exist_ok=True)
-        shutil.copy(os.path.join(ROOT, s), dst)
+    (tmp_path / "profiles" / "traffic_x.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("nearest+coop", "C3", "q16", 10)[0] == rec["traffic_bytes_per_launch"]
-    with open(tmp_path / rec["sources"][0], "a") as f:
-        f.write("\n// edited\n")
+    assert bench.measured_traffic("nearest+coop", "C3", "q16", 10) == \
+        (123456789, os.path.join("profiles", "traffic_x.json"))
+    assert bench.measured_traffic("nearest+coop", "C3", "fp32", 10) == (None, None)
+    with open(tmp_path / sources[0], "a") as f:
+        f.write("// edited\n")
     assert bench.measured_traffic("nearest+coop", "C3", "q16", 10) == (None, None)
 
 

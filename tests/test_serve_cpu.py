@@ -71,7 +71,10 @@ def test_radius_two_phases_and_host_release_backpressure():
     for t in tickets:
         r = s.wait(t)
         assert r["status"] == abx.OK and r["total"] == 10 * 200
-        assert r["t_device"] == pytest.approx(2 * 200 * 100e-9)    # count and fill phases
+        # count and fill phases; a count that was sent back to the queue (its fill
+        # waited on the others' host space) ran once more
+        phases = r["t_device"] / (200 * 100e-9)
+        assert phases == pytest.approx(round(phases)) and round(phases) >= 2
         done.append(r)
         s.release(t)
     assert s.stats()["host_high_water"] <= 64 * 1024
