@@ -165,20 +165,32 @@ def main():
     total_hits = int(idx.numel())
     rec = {"cap": total_hits}
 
-    abx.timing_reset()
-    abx.timing_enable(True)
+    # the timed steps: the library's per-kernel events are off, so nothing
+    # but the path itself runs between the synchronisations
+    abx.timing_enable(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         t, off, idx, ki, kd = step(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    abx.timing_enable(False)
 
     ms_step = 1e3 * wall / args.steps
     phases = np.array([[a.elapsed_time(b) for a, b in zip(ev[:-1], ev[1:])] for ev in rec["ev"]])
     step_ms = phases.sum(axis=1)
     build_ms, rad_ms, knn_ms = np.median(phases, axis=0)
+
+    # the same steps again with HIP events around every kernel launch (on the
+    # launch stream): per-kernel durations for the roofline
+    abx.timing_reset()
+    abx.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t, off, idx, ki, kd = step()
+    torch.cuda.synchronize()
+    ms_step_instrumented = 1e3 * (time.perf_counter() - t0) / args.steps
+    abx.timing_enable(False)
 
     kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_mid", "refit_top", "agglo", "agglo_mid",
                "agglo_top", "quantise",
@@ -277,6 +289,7 @@ def main():
         "unit": "queries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
+        "ms_per_step_instrumented": round(ms_step_instrumented, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['desc']}", "n": n, "m": m, "k": k,
@@ -314,7 +327,8 @@ def main():
         out["other_format"] = {"nodes": other, **res}
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pts_np, q_np, r, k, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(pts_np, q_np, r, k, args.cpu_seconds,
+                                           stratify=args.workload == "C3")
 
     if args.serve_requests > 0 and args.workload == "C3":
         del t, off, idx, ki, kd
@@ -550,42 +564,71 @@ def bench_serving(args, standalone):
     return out
 
 
-def cpu_baseline(pts, q, r, k, budget_s):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def baseline_sample(q, size, stratify, seed=7):
+    """Seeded query rows: uniform, or (C3) stratified like the workload's
+    extremes -- 70 % uniform, 10 % nearest the centre (the longest nearest
+    walks), 10 % nearest the corners, 10 % within 2e-3 of the shell."""
+    rng = np.random.default_rng(seed)
+    if not stratify:
+        return rng.choice(q.shape[0], size, replace=False)
+    nrm = np.linalg.norm(q.astype(np.float64), axis=1)
+    tenth = max(size // 10, 1)
+    shell = np.nonzero(np.abs(nrm - 1.0) < 2e-3)[0]
+    parts = [np.argpartition(nrm, tenth)[:tenth], np.argpartition(-nrm, tenth)[:tenth],
+             rng.choice(shell, min(tenth, shell.shape[0]), replace=False)]
+    taken = np.concatenate(parts)
+    rest = np.setdiff1d(rng.choice(q.shape[0], size, replace=False), taken)[:size - taken.shape[0]]
+    return np.concatenate([taken, rest])
+
+
+def cpu_baseline(pts, q, r, k, budget_s, stratify=False):
     """The oracle (brute force, double precision, all host threads) on a
-    seeded sample of the same queries: radius + nearest, rate in queries/s."""
+    seeded sample of the same queries: radius + nearest, rate in queries/s,
+    the median of three runs over the same sample (sized so that one run
+    takes about a third of the budget); then the same on one thread."""
     import oracle
     oracle.build_library()
-    rng = np.random.default_rng(7)
-    sel = rng.permutation(q.shape[0])
-    done, t_used, chunk = 0, 0.0, 16
-    while t_used < budget_s and done + chunk <= sel.shape[0]:
-        qq = q[sel[done:done + chunk]]
+
+    def rate(rows):
+        qq = q[rows]
         a = time.perf_counter()
         oracle.spatial(pts, oracle.POINTS, qq, oracle.WITHIN, radius=r)
         oracle.nearest(pts, oracle.POINTS, qq, k)
-        t_used += time.perf_counter() - a
-        done += chunk
-        chunk = min(chunk * 2, 256)
+        return 2 * rows.shape[0] / (time.perf_counter() - a)
+
+    # size the sample from a short probe of random rows
+    probe = np.random.default_rng(5).choice(q.shape[0], 32, replace=False)
+    est = rate(probe) / 2
+    size = int(min(max(est * budget_s / 3, 64), q.shape[0]))
+    rows = baseline_sample(q, size, stratify)
+    runs = [rate(rows) for _ in range(3)]
     cores = oracle.num_threads()
-    # the same oracle on one host thread, over the next queries of the sample
     oracle.set_num_threads(1)
-    done1, t1, chunk = 0, 0.0, 2
     try:
-        while t1 < budget_s / 4 and done + done1 + chunk <= sel.shape[0]:
-            qq = q[sel[done + done1:done + done1 + chunk]]
-            a = time.perf_counter()
-            oracle.spatial(pts, oracle.POINTS, qq, oracle.WITHIN, radius=r)
-            oracle.nearest(pts, oracle.POINTS, qq, k)
-            t1 += time.perf_counter() - a
-            done1 += chunk
+        rows1 = rows[np.random.default_rng(8).choice(rows.shape[0], max(8, min(rows.shape[0], size // cores)),
+                                                     replace=False)]
+        runs1 = [rate(rows1) for _ in range(3)]
     finally:
         oracle.set_num_threads(cores)
-    return {"value": round(2 * done / t_used, 2), "unit": "queries/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{done} seeded queries of the same workload, each answered by brute-force "
-                      f"radius and k={k} nearest over all {pts.shape[0]} points ({t_used:.1f} s)",
-            "value_1thread": round(2 * done1 / t1, 2) if t1 > 0 else None,
-            "sample_1thread": f"{done1} further queries of the sample on one thread ({t1:.1f} s)"}
+    kind = "stratified (70 % uniform, 10 % centre, 10 % corners, 10 % shell)" if stratify else "uniform"
+    return {"value": round(float(np.median(runs)), 2), "unit": "queries/s", "cores": cores,
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{rows.shape[0]} seeded queries of the same workload, {kind}, each answered by "
+                      f"brute-force radius and k={k} nearest over all {pts.shape[0]} points; median of "
+                      f"3 runs ({', '.join(f'{x:.1f}' for x in runs)} queries/s)",
+            "value_1thread": round(float(np.median(runs1)), 2),
+            "sample_1thread": f"{rows1.shape[0]} queries of the sample on one thread, median of 3 runs"}
 
 
 if __name__ == "__main__":

@@ -53,7 +53,9 @@ typedef enum {
   ABX_ERR_OVERFLOW = 4,      /* a size or result count reaches 2^31        */
   ABX_ERR_HIP = 5,           /* a HIP runtime call failed                  */
   ABX_ERR_UNSUPPORTED = 6,   /* valid request the library does not handle  */
-  ABX_PENDING = 7            /* (server) the request has not completed yet */
+  ABX_PENDING = 7,           /* (server) the request has not completed yet */
+  ABX_ERR_DEVICE = 8         /* a bounded wait between workgroups gave up
+                                (the sort's look-back): results not valid  */
 } abx_status;
 
 /* Primitives (section 2.1 "Construct AABBs": a point is a degenerate box). */
@@ -162,7 +164,9 @@ typedef struct {
  *   index), Karras (2012) hierarchy over the index-augmented codes, atomic
  *   bottom-up refit of the internal boxes (and quantisation for Q16).
  *   Blocks the host once at the end to read the NaN flag and tree height.
- *   Returns ABX_ERR_INVALID_INPUT for NaN/Inf coordinates (no handle).
+ *   Returns ABX_ERR_INVALID_INPUT for NaN/Inf coordinates (no handle), and
+ *   ABX_ERR_DEVICE (no handle) if a tile of the sort stopped waiting for
+ *   its predecessors' counts (see abx_set_sort_spin_limit).
  *   `*out` receives a new handle; release it with abx_bvh_destroy.
  * abx_bvh_destroy: frees the host handle only (tree memory is the caller's). */
 abx_status abx_bvh_build_sizes(const abx_primitives *prims, const abx_build_options *opts,
@@ -277,13 +281,30 @@ abx_status abx_query_nearest_stats(const abx_bvh *bvh, const float *points, int6
  *   x as the most significant bit of each triple (section 2.1).
  * abx_radix_sort_pairs: stable LSD radix sort of n (key, value) pairs on the
  *   low `key_bits` bits (keys uint32 when key_bits <= 32, else uint64;
- *   values int32, or the identity 0..n-1 when vals_in is NULL). */
+ *   values int32, or the identity 0..n-1 when vals_in is NULL).  Each pass
+ *   is one launch in which a tile of keys waits for the digit counts of the
+ *   tiles before it (section 2.1 "Sort the bounding boxes").  That wait is
+ *   bounded: a tile that gives up records it in the scratch buffer and the
+ *   sort completes with an invalid (though in-bounds) output.
+ * abx_radix_sort_check: blocks the host until the stream has passed a sort
+ *   on `scratch` (same n, key_bits) and returns ABX_ERR_DEVICE if one of its
+ *   tiles gave up, else ABX_OK.  (The library's own sorts act on it: a
+ *   build fails with ABX_ERR_DEVICE; a query ordering falls back to the
+ *   caller's order, which gives the same results.)
+ * abx_set_sort_spin_limit: polls of a predecessor that has published nothing
+ *   before a tile gives up (default 2^26, far above any real wait; < 0
+ *   restores it; 0 gives up at the first such poll, so tests can force the
+ *   failure path with every kernel still ending normally).  Process-wide;
+ *   returns the previous value. */
 abx_status abx_morton_codes(abx_prim_kind kind, const float *prims, int64_t n, const float *scene,
                             int32_t bits, uint64_t *codes, abx_stream_t stream);
 abx_status abx_radix_sort_sizes(int64_t n, int32_t key_bits, size_t *scratch_bytes /*host*/);
 abx_status abx_radix_sort_pairs(const void *keys_in, const int32_t *vals_in, int64_t n,
                                 int32_t key_bits, void *keys_out, int32_t *vals_out,
                                 void *scratch, size_t scratch_bytes, abx_stream_t stream);
+abx_status abx_radix_sort_check(const void *scratch, int64_t n, int32_t key_bits,
+                                abx_stream_t stream);
+int64_t abx_set_sort_spin_limit(int64_t polls);
 
 /* -- batched forest --------------------------------------------------------------
  * T independent point sets ("trees", 1 <= T <= 512) of uneven sizes, built
@@ -332,7 +353,10 @@ abx_status abx_forest_build(const abx_forest_primitives *prims, void *tree_mem, 
                             abx_forest **out /*host*/);
 /* Waits for the stream and reports the construction status:
  * ABX_ERR_INVALID_INPUT for a NaN/Inf coordinate, ABX_ERR_UNSUPPORTED for a
- * tree deeper than the traversal stacks, else ABX_OK. */
+ * tree deeper than the traversal stacks, ABX_ERR_DEVICE if the sort gave up
+ * (abx_radix_sort_check), else ABX_OK.  A forest query over a forest whose
+ * construction failed walks nothing and leaves its rows unwritten (its
+ * kernels read the status on the device, so graph replays are safe too). */
 abx_status abx_forest_check(const abx_forest *f, abx_stream_t stream);
 abx_status abx_forest_destroy(abx_forest *f);
 /* Scratch bytes of a forest nearest query, and (host) the total number of
@@ -455,9 +479,11 @@ double abx_server_now(void);
 
 /* -- diagnostics -------------------------------------------------------------
  * abx_timing_enable(1) brackets every kernel launch with HIP events on the
- *   launch stream; abx_timing_get(name) returns the summed milliseconds and
- *   launch count of the kernels called `name` since the last reset (the
- *   host waits on the events).  Not thread safe; for measurement only. */
+ *   launch stream (not on a stream that is being captured into a graph);
+ *   abx_timing_get(name) returns the summed milliseconds and launch count
+ *   of the kernels called `name` since the last reset (the host waits on
+ *   the events).  The switch and the totals are process-wide and may be
+ *   used from any thread; for measurement only. */
 const char *abx_status_string(abx_status s);
 int abx_last_hip_error(void);
 const char *abx_version(void);

@@ -28,7 +28,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libabx.so")
 
 # status codes (include/abx.h)
-OK, ERR_INVALID_ARG, ERR_INVALID_INPUT, ERR_CAPACITY, ERR_OVERFLOW, ERR_HIP, ERR_UNSUPPORTED, PENDING = range(8)
+(OK, ERR_INVALID_ARG, ERR_INVALID_INPUT, ERR_CAPACITY, ERR_OVERFLOW, ERR_HIP, ERR_UNSUPPORTED, PENDING,
+ ERR_DEVICE) = range(9)
 PRIM_POINTS, PRIM_BOXES = 0, 1
 NODES_FP32, NODES_Q16 = 0, 1
 PRED_WITHIN, PRED_INTERSECTS_BOX = 0, 1
@@ -144,6 +145,7 @@ def _lib():
             "abx_morton_codes": [C.c_int, vp, i64, vp, i32, vp, vp],
             "abx_radix_sort_sizes": [i64, i32, P(sz)],
             "abx_radix_sort_pairs": [vp, vp, i64, i32, vp, vp, vp, sz, vp],
+            "abx_radix_sort_check": [vp, i64, i32, vp],
             "abx_timing_get": [C.c_char_p, P(C.c_double), P(i64)],
             "abx_forest_build_sizes": [P(ForestPrimitives), P(sz), P(sz)],
             "abx_forest_build": [P(ForestPrimitives), vp, sz, vp, sz, vp, P(vp)],
@@ -179,6 +181,8 @@ def _lib():
         L.abx_server_now.restype = C.c_double
         L.abx_set_nearest_budget.argtypes = [C.c_int64]
         L.abx_set_nearest_budget.restype = C.c_int64
+        L.abx_set_sort_spin_limit.argtypes = [C.c_int64]
+        L.abx_set_sort_spin_limit.restype = C.c_int64
         L.abx_timing_enable.argtypes = [C.c_int]
         L.abx_timing_enable.restype = None
         L.abx_timing_reset.restype = None
@@ -432,8 +436,10 @@ def morton_codes(prims, scene, bits, kind=None):
     return codes
 
 
-def radix_sort_pairs(keys, key_bits, vals=None):
-    """Stable radix sort of (key, value) pairs; keys int32 (<=32 bits) or int64."""
+def radix_sort_pairs(keys, key_bits, vals=None, check=True):
+    """Stable radix sort of (key, value) pairs; keys int32 (<=32 bits) or int64.
+    With ``check`` the host waits for the sort and raises AbxError
+    (ERR_DEVICE) if a tile gave up waiting for its predecessors."""
     L = _lib()
     n = keys.numel()
     keys = keys.contiguous()
@@ -445,7 +451,17 @@ def radix_sort_pairs(keys, key_bits, vals=None):
     vin = None if vals is None else vals.contiguous()
     _check(L.abx_radix_sort_pairs(_ptr(keys), _ptr(vin), n, int(key_bits), _ptr(kout), _ptr(vout),
                                   _ptr(scratch), sb.value, _stream()), "abx_radix_sort_pairs")
+    if check:
+        _check(L.abx_radix_sort_check(_ptr(scratch), n, int(key_bits), _stream()),
+               "abx_radix_sort_check")
     return kout, vout
+
+
+def set_sort_spin_limit(polls):
+    """Polls of an unpublished predecessor before a sort tile gives up
+    (< 0 restores the default; 0 forces the give-up, for tests).  Returns the
+    previous value."""
+    return int(_lib().abx_set_sort_spin_limit(int(polls)))
 
 
 class ForestPlan:

@@ -20,7 +20,7 @@ abx_status launch_morton(int kind, const float *prims, int64_t n, const float *s
                          void *codes, bool wide, hipStream_t s);
 abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
                          int32_t *parent_leaf, int32_t *parent_int, int32_t *other_end,
-                         uint32_t *flags, hipStream_t s);
+                         uint32_t *flags, const TreeHeader *hdr, hipStream_t s);
 abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
                         const int32_t *parent_leaf, const int32_t *parent_int,
                         const int32_t *other_end, NodeF32 *nodes, uint32_t *flags,
@@ -54,6 +54,7 @@ int max_tree_depth();
 // node visits after which a nearest query leaves the one-lane pass for the
 // cooperative pass (abx_set_nearest_budget)
 std::atomic<int64_t> g_nearest_budget{22528};
+extern std::atomic<uint32_t> g_sort_spin_limit;  // sort.hip
 int64_t nearest_budget() { return g_nearest_budget.load(std::memory_order_relaxed); }
 
 namespace {
@@ -64,7 +65,7 @@ struct Pending {
   std::string name;
   hipEvent_t a, b;
 };
-bool g_timing = false;
+std::atomic<bool> g_timing{false};
 std::mutex g_timing_mu;  // launches may come from the server's scheduler thread
 std::vector<Pending> g_pending;
 std::map<std::string, std::pair<double, int64_t>> g_acc;
@@ -233,6 +234,7 @@ abx_status order_queries(const abx_bvh *b, const float *data, int64_t m, int wid
   ABX_TRY(launch_query_codes(b, data, m, width, codes, s));
   ABX_TRY(radix_sort(codes, nullptr, m, 30, scratch + L.sorted, ord, scratch + L.sort,
                      radix_sort_scratch_bytes(m, 30), s));
+  ABX_TRY(order_guard(radix_sort_err_word(scratch + L.sort, m, 30), ord, m, s));
   *order = ord;
   return ABX_OK;
 }
@@ -297,14 +299,18 @@ abx_status hip_fail(hipError_t e) {
   return ABX_ERR_HIP;
 }
 
-namespace {
-bool g_capturing = false;
+// whether work enqueued on `s` is being captured into a graph (the stream's
+// own state: captures on other streams or threads do not matter)
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
 }
-bool graph_capturing() { return g_capturing; }
-void set_graph_capturing(bool on) { g_capturing = on; }
 
 // no events inside a graph capture: timing is for eager launches only
-bool timing_on() { return g_timing && !g_capturing; }
+bool timing_on(hipStream_t s) {
+  return g_timing.load(std::memory_order_relaxed) && !stream_capturing(s);
+}
 
 void timing_record(const char *name, hipEvent_t a, hipEvent_t b) {
   std::lock_guard<std::mutex> lk(g_timing_mu);
@@ -329,6 +335,7 @@ const char *abx_status_string(abx_status s) {
     case ABX_ERR_HIP: return "HIP runtime error";
     case ABX_ERR_UNSUPPORTED: return "unsupported request";
     case ABX_PENDING: return "pending";
+    case ABX_ERR_DEVICE: return "a bounded device wait gave up (results not valid)";
   }
   return "unknown status";
 }
@@ -339,10 +346,10 @@ int64_t abx_set_nearest_budget(int64_t visits) {
   return g_nearest_budget.exchange(visits > 0 ? visits : INT64_MAX);
 }
 
-void abx_timing_enable(int on) { g_timing = on != 0; }
+void abx_timing_enable(int on) { g_timing.store(on != 0, std::memory_order_relaxed); }
 
-static void timing_flush() {
-  std::lock_guard<std::mutex> lk(g_timing_mu);
+// caller holds g_timing_mu
+static void timing_flush_locked() {
   for (auto &p : g_pending) {
     float ms = 0.0f;
     if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -357,13 +364,15 @@ static void timing_flush() {
 }
 
 void abx_timing_reset(void) {
-  timing_flush();
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  timing_flush_locked();
   g_acc.clear();
 }
 
 abx_status abx_timing_get(const char *kernel, double *ms, int64_t *launches) {
   if (!kernel || !ms || !launches) return ABX_ERR_INVALID_ARG;
-  timing_flush();
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  timing_flush_locked();
   auto it = g_acc.find(kernel);
   *ms = it == g_acc.end() ? 0.0 : it->second.first;
   *launches = it == g_acc.end() ? 0 : it->second.second;
@@ -411,8 +420,10 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
   uint32_t *flags = reinterpret_cast<uint32_t *>(sc + L.flags);
   if (n > 0) {
     ABX_TRY(launch_morton(kind, prims->data, n, hdr->scene, L.bits, sc + L.codes, L.wide, s));
+    // a look-back that gives up marks the header; the refit then skips
     ABX_TRY(radix_sort(sc + L.codes, nullptr, n, 3 * L.bits, sc + L.sorted, perm, sc + L.sort,
-                       radix_sort_scratch_bytes(n, 3 * L.bits), s));
+                       radix_sort_scratch_bytes(n, 3 * L.bits), s,
+                       reinterpret_cast<uint32_t *>(&hdr->bad), kBadSort));
     uint32_t *fcount = reinterpret_cast<uint32_t *>(sc + L.frontier);
     int32_t *frontier = reinterpret_cast<int32_t *>(sc + L.frontier + 256);
     if (agglo) {
@@ -424,7 +435,7 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
     int32_t *pre = nullptr;
     if (!agglo) {
       ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, fnodes, parent_leaf, parent_int, other_end,
-                            flags, s));
+                            flags, hdr, s));
       ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, parent_leaf, parent_int, other_end,
                            fnodes, flags, hdr, tree + L.leaves_off, frontier, fcount, s));
       // depth-first order of the Q16 nodes (written by the quantisation);
@@ -443,6 +454,7 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
   TreeHeader h;
   ABX_HIP(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
   ABX_HIP(hipStreamSynchronize(s));
+  if (h.bad & kBadSort) return ABX_ERR_DEVICE;
   if (h.bad & 1) return ABX_ERR_INVALID_INPUT;
   if (h.bad & 4) return ABX_ERR_UNSUPPORTED;  // refit bound exceeded (malformed hierarchy)
   if (h.bad & 8) return ABX_ERR_UNSUPPORTED;  // depth-first order out of range (too deep)
@@ -719,6 +731,24 @@ abx_status abx_radix_sort_pairs(const void *keys_in, const int32_t *vals_in, int
                                 size_t scratch_bytes, abx_stream_t stream) {
   return radix_sort(keys_in, vals_in, n, key_bits, keys_out, vals_out, scratch, scratch_bytes,
                     reinterpret_cast<hipStream_t>(stream));
+}
+
+abx_status abx_radix_sort_check(const void *scratch, int64_t n, int32_t key_bits,
+                                abx_stream_t stream) {
+  if (n < 0 || key_bits < 1 || key_bits > 64) return ABX_ERR_INVALID_ARG;
+  if (n <= 1) return ABX_OK;
+  if (!scratch) return ABX_ERR_INVALID_ARG;
+  const uint32_t *w = radix_sort_err_word(const_cast<void *>(scratch), n, key_bits);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint32_t v = 0;
+  ABX_HIP(hipMemcpyAsync(&v, w, sizeof(v), hipMemcpyDeviceToHost, s));
+  ABX_HIP(hipStreamSynchronize(s));
+  return v ? ABX_ERR_DEVICE : ABX_OK;
+}
+
+int64_t abx_set_sort_spin_limit(int64_t polls) {
+  const uint32_t v = polls < 0 ? (1u << 26) : (uint32_t)std::min<int64_t>(polls, UINT32_MAX);
+  return g_sort_spin_limit.exchange(v);
 }
 
 }  // extern "C"

@@ -31,12 +31,14 @@ struct TreeHeader {
   float q_origin[3];  // Q16 grid: x = fmaf(q, q_scale, q_origin)
   float q_scale[3];
   int32_t bad;        // 1: NaN/inf coordinate or inverted box; 2: Q16 grid overflow; 4: refit
-                      // bound or frontier exceeded; 8: depth-first order out of range
+                      // bound or frontier exceeded; 8: depth-first order out of range;
+                      // kBadSort: the sort's look-back gave up (hierarchy and refit skipped)
   int32_t height;     // longest root-to-leaf path (edges)
   int32_t root;       // internal node at the root (0 for the Karras numbering)
   int32_t pad[46];
 };
 static_assert(sizeof(TreeHeader) == 256, "header is 256 B");
+constexpr int32_t kBadSort = 16;
 
 // FP32 internal node, 64 B: four 16-B words
 //   a = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)
@@ -113,7 +115,8 @@ __device__ __forceinline__ float deq(uint32_t q, float scale, float origin) {
 // Host side.
 // ---------------------------------------------------------------------------
 abx_status hip_fail(hipError_t e);  // records e for abx_last_hip_error
-bool timing_on();
+bool stream_capturing(hipStream_t s);
+bool timing_on(hipStream_t s);      // event timing enabled and `s` not capturing
 void timing_record(const char *name, hipEvent_t a, hipEvent_t b);
 
 #define ABX_TRY(expr)                         \
@@ -133,7 +136,8 @@ void timing_record(const char *name, hipEvent_t a, hipEvent_t b);
 template <typename F>
 abx_status launch(const char *name, hipStream_t s, F &&f) {
   hipEvent_t a = nullptr, b = nullptr;
-  if (timing_on()) {
+  const bool timed = timing_on(s);
+  if (timed) {
     ABX_HIP(hipEventCreate(&a));
     ABX_HIP(hipEventCreate(&b));
     ABX_HIP(hipEventRecord(a, s));
@@ -141,7 +145,7 @@ abx_status launch(const char *name, hipStream_t s, F &&f) {
   f();
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e);
-  if (timing_on()) {
+  if (timed) {
     ABX_HIP(hipEventRecord(b, s));
     timing_record(name, a, b);
   }
@@ -156,11 +160,19 @@ inline unsigned grid_for(int64_t work, int per_block) {
 // fill kernel (graph-safe replacement for hipMemsetAsync)
 abx_status fill_u32(void *p, uint32_t value, size_t count, hipStream_t s);
 
-// radix sort (sort.hip)
+// radix sort (sort.hip).  A look-back wait that gives up marks a word of the
+// sort's own scratch (cleared by every sort, found with radix_sort_err_word,
+// which is NULL when n <= 1: nothing waits) and, if err is given, ORs
+// err_bit into *err: the output is then not a valid permutation, though
+// every store stayed inside the buffers.
 size_t radix_sort_scratch_bytes(int64_t n, int key_bits);
 abx_status radix_sort(const void *keys_in, const int32_t *vals_in, int64_t n, int key_bits,
                       void *keys_out, int32_t *vals_out, void *scratch, size_t scratch_bytes,
-                      hipStream_t s);
+                      hipStream_t s, uint32_t *err = nullptr, uint32_t err_bit = 1);
+uint32_t *radix_sort_err_word(void *scratch, int64_t n, int key_bits);
+// after a sort into order[0..m): if *err is set, order becomes the identity
+// (queries in input order give the same results, only slower)
+abx_status order_guard(const uint32_t *err, int32_t *order, int64_t m, hipStream_t s);
 
 // exclusive scan of int32 counts into int32 offsets[0..m] (scan.hip);
 // total (int64) is written to *d_total

@@ -218,9 +218,12 @@ __global__ __launch_bounds__(kBuildBlock) void k_karras(const K *__restrict__ ke
                                                         int32_t *__restrict__ parent_leaf,
                                                         int32_t *__restrict__ parent_int,
                                                         int32_t *__restrict__ other_end,
-                                                        uint32_t *__restrict__ flags) {
+                                                        uint32_t *__restrict__ flags,
+                                                        const TreeHeader *__restrict__ hdr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n - 1) return;
+  // the searches stay inside [i, j] only over sorted keys: after a failed
+  // sort nothing is built (the refit skips as well)
+  if (i >= n - 1 || (hdr->bad & kBadSort)) return;
   const K ki = keys[i];
   const int d = delta(keys, n, i, ki, i + 1) - delta(keys, n, i, ki, i - 1) >= 0 ? 1 : -1;
   const int dmin = delta(keys, n, i, ki, i - d);
@@ -296,6 +299,9 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_local(
     const int32_t *__restrict__ parent_leaf, const int32_t *__restrict__ parent_int,
     const int32_t *__restrict__ other_end, NodeF32 *nodes, TreeHeader *hdr, void *q16_leaves,
     int32_t *__restrict__ frontier, uint32_t *__restrict__ frontier_count, uint32_t frontier_cap) {
+  // after a failed sort the permutation and hierarchy are not valid: the
+  // whole grid exits (the frontier stays empty, so the later phases do too)
+  if (hdr->bad & kBadSort) return;
   __shared__ uint32_t s_cnt[kRefitChunk];
   for (int i = threadIdx.x; i < kRefitChunk; i += kRefitThreads) s_cnt[i] = 0;
   __syncthreads();
@@ -527,6 +533,7 @@ __global__ __launch_bounds__(kRefitThreads) void k_agglo_local(
     int64_t n, NodeF32 *nodes, int32_t *range_lo, int32_t *range_hi, uint32_t *__restrict__ flags,
     TreeHeader *hdr, void *q16_leaves, int32_t *__restrict__ frontier,
     uint32_t *__restrict__ frontier_count, uint32_t frontier_cap) {
+  if (hdr->bad & kBadSort) return;  // as in k_refit_local
   __shared__ uint32_t s_cnt[kRefitChunk];
   for (int i = threadIdx.x; i < kRefitChunk; i += kRefitThreads) s_cnt[i] = 0;
   __syncthreads();
@@ -864,17 +871,17 @@ abx_status launch_morton(int kind, const float *prims, int64_t n, const float *s
 
 abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
                          int32_t *parent_leaf, int32_t *parent_int, int32_t *other_end,
-                         uint32_t *flags, hipStream_t s) {
+                         uint32_t *flags, const TreeHeader *hdr, hipStream_t s) {
   if (n < 2) return ABX_OK;
   const unsigned g = grid_for(n - 1, kBuildBlock);
   if (wide)
     return launch("karras", s, [&] {
       k_karras<uint64_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint64_t *>(keys), n, nodes,
-                                                   parent_leaf, parent_int, other_end, flags);
+                                                   parent_leaf, parent_int, other_end, flags, hdr);
     });
   return launch("karras", s, [&] {
     k_karras<uint32_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint32_t *>(keys), n, nodes,
-                                                 parent_leaf, parent_int, other_end, flags);
+                                                 parent_leaf, parent_int, other_end, flags, hdr);
   });
 }
 

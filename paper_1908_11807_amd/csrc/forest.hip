@@ -279,6 +279,7 @@ __attribute__((amdgpu_waves_per_eu(forest_waves_per_eu(K)))) void k_forest_neare
                                                                  uint32_t *__restrict__ queue, int grab) {
   __shared__ int32_t s_node[kLdsDepthNearest * kForestBlock];
   __shared__ float s_dist[kLdsDepthNearest * kForestBlock];
+  if (tree_unusable(t)) return;  // abx_forest_check reports why; rows stay unwritten
   resolve_qframe(t);
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t tiles = (M + kWave - 1) / kWave;

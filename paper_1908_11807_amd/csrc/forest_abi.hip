@@ -32,7 +32,7 @@ int forest_max_trees();
 // build.hip
 abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
                          int32_t *parent_leaf, int32_t *parent_int, int32_t *other_end,
-                         uint32_t *flags, hipStream_t s);
+                         uint32_t *flags, const TreeHeader *hdr, hipStream_t s);
 abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
                         const int32_t *parent_leaf, const int32_t *parent_int,
                         const int32_t *other_end, NodeF32 *nodes, uint32_t *flags,
@@ -42,8 +42,6 @@ abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, TreeHeader 
                            const int32_t *pre, NodeQ16 *dst, hipStream_t s);
 size_t refit_frontier_cap(int64_t n);
 int max_tree_depth();
-bool graph_capturing();
-void set_graph_capturing(bool on);
 
 namespace {
 
@@ -182,6 +180,7 @@ TreeArgs forest_tree_args(const abx_forest *f) {
   t.n = f->N;
   t.scene_dev = hdr->scene;
   t.qframe = hdr->q_origin;  // q_origin[3] then q_scale[3]
+  t.guard = hdr;             // the query exits if the construction failed
   return t;
 }
 
@@ -246,8 +245,9 @@ abx_status abx_forest_build(const abx_forest_primitives *prims, void *tree_mem, 
     int32_t *parent_int = reinterpret_cast<int32_t *>(sc + L.parent_int);
     uint32_t *flags = reinterpret_cast<uint32_t *>(sc + L.flags);
     ABX_TRY(radix_sort(sc + L.keys, nullptr, N, kForestKeyBits, sc + L.sorted, perm, sc + L.sort,
-                       radix_sort_scratch_bytes(N, kForestKeyBits), s));
-    ABX_TRY(launch_karras(true, sc + L.sorted, N, fnodes, parent_leaf, parent_int, other_end, flags, s));
+                       radix_sort_scratch_bytes(N, kForestKeyBits), s,
+                       reinterpret_cast<uint32_t *>(&hdr->bad), kBadSort));
+    ABX_TRY(launch_karras(true, sc + L.sorted, N, fnodes, parent_leaf, parent_int, other_end, flags, hdr, s));
     ABX_TRY(launch_refit(ABX_PRIM_POINTS, q16, prims->data, perm, N, parent_leaf, parent_int, other_end,
                          fnodes, flags, hdr, tree + L.leaves,
                          reinterpret_cast<int32_t *>(sc + L.frontier + 256),
@@ -279,6 +279,7 @@ abx_status abx_forest_check(const abx_forest *f, abx_stream_t stream) {
   TreeHeader h;
   ABX_HIP(hipMemcpyAsync(&h, f->tree, sizeof(h), hipMemcpyDeviceToHost, s));
   ABX_HIP(hipStreamSynchronize(s));
+  if (h.bad & kBadSort) return ABX_ERR_DEVICE;
   if (h.bad & 1) return ABX_ERR_INVALID_INPUT;
   if (h.bad & 6) return ABX_ERR_UNSUPPORTED;
   if (h.height + 8 >= max_tree_depth()) return ABX_ERR_UNSUPPORTED;
@@ -326,6 +327,7 @@ abx_status abx_forest_query_nearest(const abx_forest *f, const abx_forest_querie
                               qtree, s));
   ABX_TRY(radix_sort(sc + L.keys, nullptr, M, kForestQueryKeyBits, sc + L.sorted, order, sc + L.sort,
                      radix_sort_scratch_bytes(M, kForestQueryKeyBits), s));
+  ABX_TRY(order_guard(radix_sort_err_word(sc + L.sort, M, kForestQueryKeyBits), order, M, s));
   ABX_TRY(forest_launch_rows(poff, q->offsets_dev, qtree, M, T, k, reinterpret_cast<int64_t *>(sc + L.base),
                              offsets, s));
   if (M == 0 || k == 0 || f->N == 0) return ABX_OK;
@@ -341,8 +343,8 @@ abx_status abx_forest_autotune(abx_forest *f, const abx_forest_queries *q, int32
                                size_t scratch_bytes, int32_t *offsets, int32_t *indices, float *distances,
                                abx_stream_t stream, const char *json_path, abx_forest_config *best) {
   if (!f || !best) return ABX_ERR_INVALID_ARG;
-  if (graph_capturing()) return ABX_ERR_INVALID_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return ABX_ERR_INVALID_ARG;  // it times eager launches
   const int bpcs[] = {2, 4, 6, 8};
   const int grabs[] = {1, 4};
   const int64_t budgets[] = {8192, 32768, 131072};
@@ -411,7 +413,6 @@ abx_status abx_graph_begin(abx_stream_t stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (s == nullptr) return ABX_ERR_INVALID_ARG;  // the null stream cannot be captured
   ABX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-  set_graph_capturing(true);
   return ABX_OK;
 }
 
@@ -420,7 +421,6 @@ abx_status abx_graph_end(abx_stream_t stream, void **graph_exec) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s, &g);
-  set_graph_capturing(false);
   if (e != hipSuccess) return hip_fail(e);
   hipGraphExec_t x = nullptr;
   const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);

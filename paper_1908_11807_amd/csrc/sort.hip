@@ -14,10 +14,22 @@
 // carries its own payload (2-bit flag + 30-bit count), so relaxed atomics at
 // agent scope (coherent across the XCDs' L2s) suffice: no cache flushes.
 // Forward progress: a tile index is taken after the workgroup is resident,
-// so every tile waited on belongs to a running workgroup.
+// so every tile waited on belongs to a running workgroup.  The wait is still
+// bounded; a tile that gives up sets the caller's error word, publishes the
+// prefix it has (never more than the true one, so every store stays inside
+// the output) and lets its pass finish; the later passes see the word and
+// do nothing.  The result is then invalid and the callers act on the word
+// (the build fails, a query order falls back to the input order).
+#include <atomic>
+
 #include "abx_internal.h"
 
 namespace abx {
+
+// look-back polls of a predecessor that has published nothing, before the
+// tile gives up (abx_set_sort_spin_limit; 0 gives up at once, for tests)
+std::atomic<uint32_t> g_sort_spin_limit{1u << 26};
+
 namespace {
 
 constexpr int kBlock = 256;                 // 4 waves
@@ -98,7 +110,10 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
                                                      K *__restrict__ kout, int32_t *__restrict__ vout,
                                                      int64_t n, int shift, int nbits,
                                                      const uint32_t *__restrict__ digit_start,
-                                                     uint32_t *status, uint32_t *tile_ctr) {
+                                                     uint32_t *status, uint32_t *tile_ctr,
+                                                     uint32_t spin_limit, int pass,
+                                                     uint32_t *fail_pass, uint32_t *err,
+                                                     uint32_t err_bit) {
   constexpr int kItems = kItemsOf<K>, kTile = kTileOf<K>;
   __shared__ uint32_t s_cnt[kWaves][kRadix];
   __shared__ uint32_t s_loc[kRadix];
@@ -108,6 +123,15 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
   __shared__ int32_t s_vals[kTile];
   __shared__ uint32_t s_tile;
 
+  // After a pass gave up, its output is no permutation of the keys the
+  // digit histograms were taken from, so the scatter positions of a later
+  // pass would not stay inside [0, n): the later passes do nothing.  (The
+  // other tiles of the failing pass itself carry on: their successors wait
+  // for their counts.)  *fail_pass is 0, or 1 + the pass that gave up.
+  {
+    const uint32_t f = __hip_atomic_load(fail_pass, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (f != 0 && f <= (uint32_t)pass) return;
+  }
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
@@ -174,12 +198,18 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
     __hip_atomic_store(st, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int64_t j = (int64_t)tile - 1;
     // Every awaited tile belongs to a resident workgroup, so the wait ends;
-    // the spin bound (far above any real wait) only guarantees termination.
+    // the spin bound (far above any real wait) only guarantees termination,
+    // and giving up is recorded (the failed-pass word, and *err if given).
     for (uint32_t spins = 0;;) {
+      if (spins >= spin_limit) {
+        atomicMax(fail_pass, (uint32_t)pass + 1u);
+        if (err) atomicOr(err, err_bit);
+        break;
+      }
       const uint32_t w = __hip_atomic_load(status + (size_t)j * kRadix + d, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
       if ((w & ~kCountMask) == 0) {
-        if (++spins > (1u << 26)) break;
+        ++spins;
         __builtin_amdgcn_s_sleep(1);
         continue;
       }
@@ -210,8 +240,13 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
     const K kk = s_keys[i];
     const uint32_t dd = (uint32_t)(kk >> shift) & dmask;
     const uint32_t o = s_gbase[dd] + (uint32_t)i;
-    kout[o] = kk;
-    vout[o] = s_vals[i];
+    // o < n whenever this pass's input is a permutation of the histogrammed
+    // keys (a tile that gave up publishes too small a prefix, never too
+    // large); the test keeps every store in bounds regardless
+    if (o < (uint64_t)n) {
+      kout[o] = kk;
+      vout[o] = s_vals[i];
+    }
   }
 }
 
@@ -225,6 +260,16 @@ __global__ void k_copy_pairs(const K *__restrict__ kin, const int32_t *__restric
   }
 }
 
+// the identity order when the sort that produced `order` gave up; the
+// workgroups exit after one load when it did not
+__global__ void k_order_guard(const uint32_t *__restrict__ err, int32_t *__restrict__ order,
+                              int64_t m) {
+  if (*err == 0) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    order[i] = (int32_t)i;
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, size_t count) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -232,7 +277,7 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t value, size_t count) {
 }
 
 struct SortLayout {
-  size_t hist, ctr, status, tmp_keys, tmp_vals, total;
+  size_t hist, ctr, err, status, tmp_keys, tmp_vals, total;
   int64_t tiles;
   int passes;
 };
@@ -248,6 +293,8 @@ SortLayout sort_layout(int64_t n, int key_bits) {
   off = align_up(off + (size_t)L.passes * kRadix * 4, 256);
   L.ctr = off;
   off = align_up(off + (size_t)L.passes * 4, 256);
+  L.err = off;  // 0, or 1 + the pass that gave up; cleared with the counters
+  off = align_up(off + 4, 256);
   L.status = off;
   off = align_up(off + (size_t)L.passes * L.tiles * kRadix * 4, 256);
   L.tmp_keys = off;
@@ -260,7 +307,7 @@ SortLayout sort_layout(int64_t n, int key_bits) {
 
 template <typename K>
 abx_status sort_impl(const K *kin, const int32_t *vin, int64_t n, int key_bits, K *kout,
-                     int32_t *vout, char *scratch, hipStream_t s) {
+                     int32_t *vout, char *scratch, uint32_t *err, uint32_t err_bit, hipStream_t s) {
   if (n <= 1) {
     if (n == 1)
       ABX_TRY(launch("sort_copy", s, [&] {
@@ -274,7 +321,9 @@ abx_status sort_impl(const K *kin, const int32_t *vin, int64_t n, int key_bits, 
   uint32_t *status = reinterpret_cast<uint32_t *>(scratch + L.status);
   K *tk = reinterpret_cast<K *>(scratch + L.tmp_keys);
   int32_t *tv = reinterpret_cast<int32_t *>(scratch + L.tmp_vals);
-  // zero histograms, tile counters and status words in one fill
+  uint32_t *fail_pass = reinterpret_cast<uint32_t *>(scratch + L.err);
+  const uint32_t spin_limit = g_sort_spin_limit.load(std::memory_order_relaxed);
+  // zero histograms, tile counters, the failed-pass word and status words in one fill
   ABX_TRY(fill_u32(hist, 0, (L.tmp_keys - L.hist) / 4, s));
   const unsigned hb = (unsigned)std::min<int64_t>(kHistBlocks, grid_for(n, kBlock * 8));
   ABX_TRY(launch("sort_hist", s, [&] {
@@ -297,12 +346,12 @@ abx_status sort_impl(const K *kin, const int32_t *vin, int64_t n, int key_bits, 
     if (p == 0 && src_v == nullptr) {
       ABX_TRY(launch("sort_onesweep", s, [&] {
         k_onesweep<K, true><<<g, kBlock, 0, s>>>(src_k, nullptr, dk, dv, n, shift, nbits, ds, stp,
-                                                 ctr + p);
+                                                 ctr + p, spin_limit, p, fail_pass, err, err_bit);
       }));
     } else {
       ABX_TRY(launch("sort_onesweep", s, [&] {
         k_onesweep<K, false><<<g, kBlock, 0, s>>>(src_k, src_v, dk, dv, n, shift, nbits, ds, stp,
-                                                  ctr + p);
+                                                  ctr + p, spin_limit, p, fail_pass, err, err_bit);
       }));
     }
     src_k = dk;
@@ -323,9 +372,20 @@ abx_status fill_u32(void *p, uint32_t value, size_t count, hipStream_t s) {
 
 size_t radix_sort_scratch_bytes(int64_t n, int key_bits) { return sort_layout(n, key_bits).total; }
 
+abx_status order_guard(const uint32_t *err, int32_t *order, int64_t m, hipStream_t s) {
+  if (!err || m <= 0) return ABX_OK;
+  const unsigned g = (unsigned)std::min<int64_t>(256, grid_for(m, 256));
+  return launch("order_guard", s, [&] { k_order_guard<<<g, 256, 0, s>>>(err, order, m); });
+}
+
+uint32_t *radix_sort_err_word(void *scratch, int64_t n, int key_bits) {
+  if (n <= 1) return nullptr;  // no look-back: nothing can give up
+  return reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + sort_layout(n, key_bits).err);
+}
+
 abx_status radix_sort(const void *keys_in, const int32_t *vals_in, int64_t n, int key_bits,
                       void *keys_out, int32_t *vals_out, void *scratch, size_t scratch_bytes,
-                      hipStream_t s) {
+                      hipStream_t s, uint32_t *err, uint32_t err_bit) {
   if (n < 0 || key_bits < 1 || key_bits > 64) return ABX_ERR_INVALID_ARG;
   if (n >= (int64_t)kCountMask) return ABX_ERR_OVERFLOW;
   if (n > 0 && (!keys_in || !keys_out || !vals_out)) return ABX_ERR_INVALID_ARG;
@@ -336,10 +396,10 @@ abx_status radix_sort(const void *keys_in, const int32_t *vals_in, int64_t n, in
   if (key_bits <= 32)
     return sort_impl<uint32_t>(static_cast<const uint32_t *>(keys_in), vals_in, n, key_bits,
                                static_cast<uint32_t *>(keys_out), vals_out,
-                               static_cast<char *>(scratch), s);
+                               static_cast<char *>(scratch), err, err_bit, s);
   return sort_impl<uint64_t>(static_cast<const uint64_t *>(keys_in), vals_in, n, key_bits,
                              static_cast<uint64_t *>(keys_out), vals_out,
-                             static_cast<char *>(scratch), s);
+                             static_cast<char *>(scratch), err, err_bit, s);
 }
 
 }  // namespace abx

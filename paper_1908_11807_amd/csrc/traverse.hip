@@ -346,6 +346,7 @@ TreeArgs tree_args(const abx_bvh *b) {
   }
   t.scene_dev = b->hdr()->scene;
   t.qframe = nullptr;
+  t.guard = nullptr;  // the build checked the header before making the handle
   return t;
 }
 

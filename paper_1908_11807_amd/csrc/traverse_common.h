@@ -31,7 +31,15 @@ struct TreeArgs {
   const float *scene_dev;  // the same scene box in device memory
   const float *qframe;     // if set: Q16 origin[3], scale[3] in device memory (read at
                            // kernel start; used where the host has not read them back)
+  const TreeHeader *guard; // if set: the construction's header, read at kernel start
+                           // (forests, whose build the host does not wait for)
 };
+
+// A tree whose construction reported a problem (any flag, or a height the
+// stacks cannot hold) is not walked: its nodes may not form a tree.
+__device__ __forceinline__ bool tree_unusable(const TreeArgs &t) {
+  return t.guard && (t.guard->bad != 0 || t.guard->height + 8 >= kMaxDepth);
+}
 
 __device__ __forceinline__ void resolve_qframe(TreeArgs &t) {
   if (t.qframe) {

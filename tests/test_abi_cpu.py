@@ -52,8 +52,9 @@ def test_exported_symbols_match_nm():
 
 def test_status_strings_and_version():
     abx, L = _lib()
-    for s in range(7):
+    for s in range(9):
         assert L.abx_status_string(s)
+    assert b"unknown" not in L.abx_status_string(8)
     assert "gfx950" in abx.version()
 
 

@@ -106,3 +106,27 @@ def test_cpu_baseline_reports_the_oracle_rate():
     import oracle
     # the thread count is restored after the one-thread sample
     assert oracle.num_threads() == out["cores"]
+
+
+def test_baseline_sample_strata():
+    from paper_1908_11807_amd import datagen
+    q = datagen.uniform_cube(50_000, 3, -1.0, 1.0)
+    rows = bench.baseline_sample(q, 1000, True)
+    assert rows.shape[0] == 1000 and np.unique(rows).shape[0] == 1000
+    nrm = np.linalg.norm(q.astype(np.float64), axis=1)
+    # the centre stratum holds the 100 queries nearest the centre
+    assert set(np.argsort(nrm)[:100]) <= set(rows.tolist())
+    assert set(np.argsort(-nrm)[:100]) <= set(rows.tolist())
+    assert np.sum(np.abs(nrm[rows] - 1.0) < 2e-3) >= 100
+    # uniform sampling without strata: distinct rows
+    r2 = bench.baseline_sample(q, 500, False)
+    assert np.unique(r2).shape[0] == 500
+
+
+def test_cpu_baseline_stratified_reports_cpu_and_runs():
+    from paper_1908_11807_amd import datagen
+    pts = datagen.shell(20000, 4)
+    q = datagen.uniform_cube(5000, 5, -1.0, 1.0)
+    out = bench.cpu_baseline(pts, q, 0.02, 10, 0.6, stratify=True)
+    assert "median of 3 runs" in out["sample"] and "stratified" in out["sample"]
+    assert out["value"] > 0 and "cpu" in out
