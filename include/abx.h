@@ -248,6 +248,25 @@ abx_status abx_query_nearest(const abx_bvh *bvh, const float *points /*[m,3]*/, 
                              int32_t *offsets /*[m+1]*/, int32_t *indices, float *distances,
                              abx_stream_t stream);
 
+/* -- nearest queries without any allocation ------------------------------
+ * For callers that cannot allocate memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The same query, the
+ * same kernels and the same results as abx_query_nearest, but the scratch is
+ * a library-owned device array of ABX_STATIC_SCRATCH_BYTES per GPU (set up
+ * when the library's code is loaded on that GPU, held until the process
+ * ends).  The caller still owns points, offsets, indices and distances.
+ * Returns ABX_ERR_CAPACITY, before launching anything, when the scratch that
+ * abx_query_nearest_sizes reports for (m, k) exceeds ABX_STATIC_SCRATCH_BYTES
+ * (about 400 000 queries).  The call allocates nothing, on the device or the
+ * host: no hipMalloc, hipFree or event (timing mode does not apply to it).
+ * All calls on one GPU share that GPU's array: calls that overlap in time on
+ * one GPU (from different streams or threads) race and their results are
+ * undefined; calls ordered on one stream are safe. */
+#define ABX_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+abx_status abx_query_nearest_static(const abx_bvh *bvh, const float *points /*[m,3]*/, int64_t m,
+                                    int32_t k, int32_t sort_queries, int32_t *offsets /*[m+1]*/,
+                                    int32_t *indices, float *distances, abx_stream_t stream);
+
 /* -- load balance of nearest queries ------------------------------------------
  * A nearest query is first walked by one lane (the paper's batched mode).  A
  * walk that exceeds `visits` internal-node visits is abandoned and the query

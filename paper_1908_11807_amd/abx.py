@@ -140,6 +140,7 @@ def _lib():
             "abx_query_spatial_1p": [vp, P(Predicates), i32, vp, sz, vp, vp, i64, vp, vp],
             "abx_query_nearest_sizes": [vp, i64, i32, P(sz)],
             "abx_query_nearest": [vp, vp, i64, i32, i32, vp, sz, vp, vp, vp, vp],
+            "abx_query_nearest_static": [vp, vp, i64, i32, i32, vp, vp, vp, vp],
             "abx_query_spatial_stats": [vp, P(Predicates), vp, sz, vp, vp],
             "abx_query_nearest_stats": [vp, vp, i64, i32, i32, vp, sz, vp, vp],
             "abx_morton_codes": [C.c_int, vp, i64, vp, i32, vp, vp],
@@ -393,6 +394,30 @@ def query_nearest(bvh, points, k, sort_queries=True):
     _check(L.abx_query_nearest(bvh.handle, _ptr(q), m, int(k), 1 if sort_queries else 0,
                                _ptr(scratch), sb.value, _ptr(offsets), _ptr(idx), _ptr(dist),
                                _stream()), "abx_query_nearest")
+    return offsets, idx, dist
+
+
+# scratch of abx_query_nearest_static, one library-owned array per GPU
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def query_nearest_static(bvh, points, k, sort_queries=True, out=None):
+    """The same query as ``query_nearest`` through the entry point that
+    allocates nothing (its scratch is the library's per-GPU array).
+    ``out`` = (offsets [m+1], indices [m,k'], distances [m,k']) to write
+    into; otherwise they are allocated here, outside the library."""
+    L = _lib()
+    q = _dev_f32(points, 3, "query points")
+    m = q.shape[0]
+    kk = max(0, min(int(k), bvh.n))
+    if out is None:
+        out = (torch.empty(m + 1, dtype=torch.int32, device=q.device),
+               torch.empty((m, kk), dtype=torch.int32, device=q.device),
+               torch.empty((m, kk), dtype=torch.float32, device=q.device))
+    offsets, idx, dist = out
+    _check(L.abx_query_nearest_static(bvh.handle, _ptr(q), m, int(k), 1 if sort_queries else 0,
+                                      _ptr(offsets), _ptr(idx), _ptr(dist), _stream()),
+           "abx_query_nearest_static")
     return offsets, idx, dist
 
 

@@ -307,9 +307,11 @@ bool stream_capturing(hipStream_t s) {
   return st != hipStreamCaptureStatusNone;
 }
 
+thread_local int g_no_events = 0;
+
 // no events inside a graph capture: timing is for eager launches only
 bool timing_on(hipStream_t s) {
-  return g_timing.load(std::memory_order_relaxed) && !stream_capturing(s);
+  return g_timing.load(std::memory_order_relaxed) && g_no_events == 0 && !stream_capturing(s);
 }
 
 void timing_record(const char *name, hipEvent_t a, hipEvent_t b) {

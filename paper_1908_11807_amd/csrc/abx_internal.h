@@ -116,8 +116,18 @@ __device__ __forceinline__ float deq(uint32_t q, float scale, float origin) {
 // ---------------------------------------------------------------------------
 abx_status hip_fail(hipError_t e);  // records e for abx_last_hip_error
 bool stream_capturing(hipStream_t s);
-bool timing_on(hipStream_t s);      // event timing enabled and `s` not capturing
+bool timing_on(hipStream_t s);      // event timing enabled, `s` not capturing, events allowed
 void timing_record(const char *name, hipEvent_t a, hipEvent_t b);
+
+// While one exists on a thread, launches from that thread create no events
+// (entry points that promise to allocate nothing).
+extern thread_local int g_no_events;
+struct NoEventsScope {
+  NoEventsScope() { ++g_no_events; }
+  ~NoEventsScope() { --g_no_events; }
+  NoEventsScope(const NoEventsScope &) = delete;
+  NoEventsScope &operator=(const NoEventsScope &) = delete;
+};
 
 #define ABX_TRY(expr)                         \
   do {                                        \
