@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C3",
                     choices=["C1", "C2", "C3", "C4", "C5", "COPY", "PAPER"])
-    ap.add_argument("--nodes", default="q16", choices=["fp32", "q16"])
+    ap.add_argument("--nodes", default="q16", choices=["fp32", "q16", "q16w"])
     ap.add_argument("--morton-bits", type=int, default=21)
     ap.add_argument("--hierarchy", default="karras", choices=["karras", "agglomerative"])
     ap.add_argument("--k", type=int, default=10)
@@ -80,11 +80,11 @@ def algorithmic_bytes(stats, node_b, leaf_b, per_query_fixed):
     return int(per_query_fixed * s.shape[0] + node_b * s[:, 0].sum() + leaf_b * s[:, 1].sum())
 
 
-def build_bytes_per_prim(node_format, morton_bits, kind_width=3, depth_first=False):
+def build_bytes_per_prim(node_format, morton_bits, kind_width=3, depth_first=False, wide_per_prim=0.0):
     """Algorithmic bytes of one build, per point primitive (chunked refit,
     8-bit radix digits; `depth_first`: the tree's nodes were renumbered in
     depth-first order, which Q16 Karras trees of 2^22 primitives and more
-    get by default)."""
+    get by default; `wide_per_prim`: 4-wide nodes written per primitive)."""
     keyb = 8 if morton_bits > 10 else 4          # 63- or 30-bit Morton keys
     passes = 8 if morton_bits > 10 else 4        # 8-bit digits
     w = 4 * kind_width                           # 12 B point (24 B box)
@@ -95,6 +95,14 @@ def build_bytes_per_prim(node_format, morton_bits, kind_width=3, depth_first=Fal
     b += keyb + 8 + 8                            # hierarchy: keys, child refs, parent + range end
     b += 4 + w + 4                               # refit, leaf: permutation, primitive, parent
     b += 4 + 4 + 64 + 28                         # refit, node: parent, range end, node, sibling
+    if node_format == "q16w":
+        b += 4 + 8 + 6 * (8 + 8 + 8)             # depth and order: init, 6 pointer-jumping rounds
+        b += 8 + 8 + 4 + 4 + 4                   # last round: words, range end, index and depth
+        b += 4 + 4 + 4                           # flags: index, depth, flag
+        b += 4 + 4                               # scan of the flags
+        b += 64 + 4 + 4 + 4 + 4                  # collapse: every binary node read once, its depth,
+        #                                          index, rank, and its rank read by its parent
+        b += 64 * wide_per_prim                  # the 4-wide nodes written
     if node_format == "q16":
         b += 64 + 32                             # quantise: read FP32 node, write Q16 node
         if depth_first:
@@ -193,7 +201,7 @@ def main():
     abx.timing_enable(False)
 
     kernels = ["morton", "sort_onesweep", "sort_hist", "karras", "refit", "refit_mid", "refit_top", "agglo", "agglo_mid",
-               "agglo_top", "quantise",
+               "agglo_top", "quantise", "preorder", "wide_flags", "wide_emit",
                "scene_partial", "query_codes", "spatial_count", "spatial_fill", "scan_tiles", "nearest",
                "nearest_coop"]
     ktimes = {}
@@ -254,7 +262,8 @@ def main():
 
     # the other two phases against the same HBM peak (algorithmic bytes)
     bpp = build_bytes_per_prim(args.nodes, args.morton_bits,
-                               depth_first=int(t.layout.node_order) == abx.ORDER_DEPTH_FIRST)
+                               depth_first=int(t.layout.node_order) == abx.ORDER_DEPTH_FIRST,
+                               wide_per_prim=int(t.layout.node_count) / n if args.nodes == "q16w" else 0.0)
     rad_bytes = alg["spatial_count"] + alg["spatial_fill"]
     phase_rooflines = {
         "build": dict(bytes_per_prim=bpp, achieved=round(bpp * n / (build_ms * 1e-3) / 1e9, 1),

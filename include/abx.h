@@ -75,8 +75,16 @@ typedef enum {
  *         leaf child's slot holds the point's float32 coordinates; box
  *         trees keep the exact float32 box in a leaf record.  Results are
  *         identical to FP32.  (The paper names quantised bounds as a way to
- *         cut BVH bandwidth, section 2 literature review.) */
-typedef enum { ABX_NODES_FP32 = 0, ABX_NODES_Q16 = 1 } abx_node_format;
+ *         cut BVH bandwidth, section 2 literature review.)
+ *   Q16W: 64 B per internal node with up to FOUR children -- the binary
+ *         tree collapsed at even depths: a node keeps its children's
+ *         children, a leaf child stays a leaf child -- quantised as Q16 and
+ *         stored in depth-first order.  A walk makes half as many dependent
+ *         node loads (the paper leaves the load balance of one thread per
+ *         query open, section 2.2; wider nodes shorten each thread's chain of
+ *         loads).  Karras hierarchy only; trees of binary height above 78
+ *         are refused (the walks' stacks).  Results are identical to FP32. */
+typedef enum { ABX_NODES_FP32 = 0, ABX_NODES_Q16 = 1, ABX_NODES_Q16W = 2 } abx_node_format;
 
 typedef struct {
   abx_prim_kind kind;
@@ -113,7 +121,8 @@ typedef struct {
   int32_t hierarchy;   /* abx_hierarchy (0: Karras) */
   int32_t node_order;  /* abx_node_order (0: automatic); DEPTH_FIRST with
                           FP32 nodes or the agglomerative hierarchy returns
-                          ABX_ERR_UNSUPPORTED */
+                          ABX_ERR_UNSUPPORTED, as do Q16W nodes with BUILD
+                          order or the agglomerative hierarchy */
 } abx_build_options;
 
 /* Spatial predicates (section 2.2, spatial traversal). */
@@ -154,6 +163,8 @@ typedef struct {
                              float lo xyz, hi xyz, its sorted position, pad */
   float q16_origin[3];    /* Q16 dequantisation: x = fmaf(q, scale, origin) */
   float q16_scale[3];
+  int64_t node_count;     /* internal nodes stored: n - 1 (binary), fewer for
+                             Q16W (node i at nodes_offset + i * node_bytes) */
 } abx_bvh_layout;
 
 /* -- construction (section 2.1) ------------------------------------------
@@ -343,7 +354,7 @@ typedef struct {
   const int64_t *offsets_host; /* host   [T+1], offsets[0] = 0, non-decreasing */
   const int64_t *offsets_dev;  /* device [T+1], same values                    */
   const float *data;           /* device [offsets[T], 3] points                 */
-  abx_node_format node_format;
+  abx_node_format node_format; /* FP32 or Q16 (Q16W: ABX_ERR_UNSUPPORTED)       */
 } abx_forest_primitives;
 
 typedef struct {
@@ -413,22 +424,34 @@ abx_status abx_graph_destroy(void *graph_exec);
 
 /* -- serving -------------------------------------------------------------------
  * Continuous batching of query requests against device-resident trees (a
- * tree is built once and queried many times, section 2.2).  A scheduler
- * thread owns `slots` HIP streams.  Requests wait in FIFO order; the head is
- * admitted as soon as a slot is free and its device reservation fits in the
- * caller's arena (the HBM budget), so requests that arrive while others run
- * start as slots and memory free up, and their kernels overlap on the
- * device.  Nearest requests run in one phase; radius requests in two (count,
- * then fill once the exact result space is reserved).  Results are copied to
- * a pinned host arena the server allocates at creation and stay valid until
- * abx_server_release.  Every request is answered by the same kernels as the
- * plain entry points, so its result does not depend on what else is in
- * flight.  Radius requests, and nearest requests of fewer than 4096
- * queries, are walked in the caller's order; larger nearest requests are
- * Morton-ordered first (at request sizes the ordering pays only for long
- * nearest walks).  Times are seconds on abx_server_now()'s steady clock.
- * Reservations (bytes, 256-B granules): queries 12m + query scratch +
- * nearest 8mk' | radius offsets 4(m+1), then 4*total for the fill.
+ * tree is built once and queried many times, section 2.2; the batched mode
+ * of section 2.2 applied across requests).  A scheduler thread owns `slots`
+ * HIP streams.  Queued requests on the same tree with the same predicate
+ * (nearest with the same k, or radius with the same r) that are small are
+ * MERGED: the first waiting one takes the later ones of its class along, up
+ * to merge_queries queries, and they run as one launch sequence over their
+ * concatenated queries; each request's rows are copied back to its own
+ * results.  Admission serves the queue in order within each size class
+ * (small / large by small_queries): a batch starts as soon as a slot is free
+ * and its device reservation fits in the caller's arena (the HBM budget);
+ * a request of one class may pass one of the other that cannot start (no
+ * memory, or slots - 1 large batches already running: one slot stays for
+ * small requests).  Requests that arrive while others run start as slots
+ * and memory free up, and their kernels overlap on the device.  Nearest
+ * batches run in one phase; radius batches in two (count, then fill once the
+ * exact result space is reserved; while a fill waits, new batches are
+ * admitted only if that space stays free).  Results are copied to a pinned
+ * host arena the server allocates at creation and stay valid until
+ * abx_server_release.  Every row is answered by the same kernels as the
+ * plain entry points, and a row depends only on its own query, so a
+ * request's result does not depend on what else is in flight or merged with
+ * it.  Radius batches, and nearest batches of fewer than 4096 queries, are
+ * walked in the caller's order; larger nearest batches are Morton-ordered
+ * first (at request sizes the ordering pays only for long nearest walks).
+ * Times are seconds on abx_server_now()'s steady clock.  Reservations
+ * (bytes, 256-B granules): per batch of M queries 12M + query scratch +
+ * nearest 8Mk' | radius offsets 4(M+1), then 4*total for the fill; per
+ * request its host results.
  * `simulate` = 1 runs the scheduler without HIP (each phase lasts
  * sim_ns_per_query * m ns, radius requests find 10 results per query): for
  * testing admission and accounting on a machine without a GPU. */
@@ -442,6 +465,11 @@ typedef struct {
   int32_t poll_us;        /* scheduler sleep when idle-polling (0: 20 us)    */
   int32_t simulate;
   double sim_ns_per_query;
+  int64_t merge_queries;  /* a merged launch holds at most this many queries
+                             (0: 32768; < 0: no merging)                     */
+  int64_t small_queries;  /* requests of at most this many queries are
+                             "small": they may be merged, and the two size
+                             classes may pass each other (0: 8192)          */
 } abx_server_config;
 
 typedef struct {
@@ -461,18 +489,21 @@ typedef struct {
   const int32_t *indices;          /* HOST [total]                          */
   const float *distances;          /* HOST [total] (nearest) or NULL        */
   double t_arrival, t_admit, t_done;
-  double t_device;                 /* GPU time of the request's phases (s):
-                                      its copies and kernels, from events on
-                                      its stream; excludes queueing and the
-                                      wait for the fill's memory            */
+  double t_device;                 /* GPU time of the phases of the request's
+                                      batch (s): copies and kernels, from
+                                      events on its stream; excludes
+                                      queueing and the wait for the fill's
+                                      memory                                */
 } abx_result;
 
 typedef struct {
   int64_t submitted, completed, failed, queries, max_in_flight, in_flight, queued;
   size_t device_high_water, host_high_water;
-  int64_t requeued;        /* radius requests sent back to the queue head after
+  int64_t requeued;        /* radius requests sent back to the queue after
                               their count: fills that waited on each other's
                               reservations (the earliest keeps its slot)   */
+  int64_t batches;         /* launch sequences: one per admitted batch of
+                              merged requests                               */
 } abx_server_stats;
 
 typedef struct abx_server abx_server;
@@ -483,7 +514,10 @@ abx_status abx_server_add_tree(abx_server *srv, const abx_bvh *tree, int32_t *id
  * the result of a request whose reservation can never fit: at admission, one
  * larger than an arena; at the fill, one whose result space does not fit
  * while nothing else holds either arena.  A fill that waits for host space
- * held by results not yet released waits for abx_server_release. */
+ * held by results not yet released waits for abx_server_release.  Merged
+ * requests can complete before requests submitted ahead of them, so a caller
+ * whose host arena cannot hold the results in flight must release results in
+ * the order they complete (poll), not wait for them in submission order. */
 abx_status abx_server_submit(abx_server *srv, const abx_request *req, uint64_t *ticket /*host*/);
 /* ABX_PENDING until the request has completed (results host-visible). */
 abx_status abx_server_poll(abx_server *srv, uint64_t ticket, abx_result *out /*host*/);

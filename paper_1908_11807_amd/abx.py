@@ -31,10 +31,11 @@ LIB_PATH = os.path.join(_HERE, "libabx.so")
 (OK, ERR_INVALID_ARG, ERR_INVALID_INPUT, ERR_CAPACITY, ERR_OVERFLOW, ERR_HIP, ERR_UNSUPPORTED, PENDING,
  ERR_DEVICE) = range(9)
 PRIM_POINTS, PRIM_BOXES = 0, 1
-NODES_FP32, NODES_Q16 = 0, 1
+NODES_FP32, NODES_Q16, NODES_Q16W = 0, 1, 2
 PRED_WITHIN, PRED_INTERSECTS_BOX = 0, 1
 
-_FORMATS = {"fp32": NODES_FP32, "q16": NODES_Q16, NODES_FP32: NODES_FP32, NODES_Q16: NODES_Q16}
+_FORMATS = {"fp32": NODES_FP32, "q16": NODES_Q16, "q16w": NODES_Q16W, NODES_FP32: NODES_FP32,
+            NODES_Q16: NODES_Q16, NODES_Q16W: NODES_Q16W}
 _HIERARCHIES = {"karras": 0, "agglomerative": 1}
 _ORDERS = {"auto": 0, "build": 1, "depth_first": 2}
 ORDER_BUILD, ORDER_DEPTH_FIRST = 1, 2
@@ -82,7 +83,8 @@ class ForestConfig(C.Structure):
 class ServerConfig(C.Structure):
     _fields_ = [("slots", C.c_int32), ("arena", C.c_void_p), ("arena_bytes", C.c_size_t),
                 ("host_bytes", C.c_size_t), ("poll_us", C.c_int32), ("simulate", C.c_int32),
-                ("sim_ns_per_query", C.c_double)]
+                ("sim_ns_per_query", C.c_double), ("merge_queries", C.c_int64),
+                ("small_queries", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -101,7 +103,7 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("queries", C.c_int64), ("max_in_flight", C.c_int64), ("in_flight", C.c_int64),
                 ("queued", C.c_int64), ("device_high_water", C.c_size_t),
-                ("host_high_water", C.c_size_t), ("requeued", C.c_int64)]
+                ("host_high_water", C.c_size_t), ("requeued", C.c_int64), ("batches", C.c_int64)]
 
 
 REQ_RADIUS, REQ_NEAREST = 0, 1
@@ -113,7 +115,8 @@ class Layout(C.Structure):
                 ("root", C.c_int32), ("node_order", C.c_int32), ("scene", C.c_float * 6),
                 ("nodes_offset", C.c_size_t), ("node_bytes", C.c_size_t),
                 ("leaves_offset", C.c_size_t), ("leaf_bytes", C.c_size_t),
-                ("q16_origin", C.c_float * 3), ("q16_scale", C.c_float * 3)]
+                ("q16_origin", C.c_float * 3), ("q16_scale", C.c_float * 3),
+                ("node_count", C.c_int64)]
 
 
 _LIB = None
@@ -258,8 +261,7 @@ class BVH:
 
     def nodes_bytes(self):
         lay = self.layout
-        ni = max(self.n - 1, 0)
-        return self.tree[lay.nodes_offset: lay.nodes_offset + ni * lay.node_bytes]
+        return self.tree[lay.nodes_offset: lay.nodes_offset + int(lay.node_count) * lay.node_bytes]
 
     def leaves_bytes(self):
         lay = self.layout
@@ -633,19 +635,21 @@ def server_now():
 class Server:
     """Continuous-batching request server over device-resident trees.
 
-    slots: concurrent requests (one HIP stream each); budget_bytes: the HBM
+    slots: concurrent batches (one HIP stream each); budget_bytes: the HBM
     arena for in-flight request data (allocated here with PyTorch and handed
     to the library); host_bytes: pinned host result arena (allocated by the
-    library).  simulate=True runs the scheduler without the GPU.
+    library); merge_queries / small_queries: merge limits (0: the library's
+    defaults; merge_queries < 0 turns merging off).  simulate=True runs the
+    scheduler without the GPU.
     """
 
     def __init__(self, slots=4, budget_bytes=1 << 30, host_bytes=1 << 30, simulate=False,
-                 sim_ns_per_query=0.0, poll_us=0, device="cuda"):
+                 sim_ns_per_query=0.0, poll_us=0, device="cuda", merge_queries=0, small_queries=0):
         L = _lib()
         self.arena = None if simulate else torch.empty(int(budget_bytes), dtype=torch.uint8, device=device)
         cfg = ServerConfig(int(slots), self.arena.data_ptr() if self.arena is not None else None,
                            int(budget_bytes), int(host_bytes), int(poll_us), 1 if simulate else 0,
-                           float(sim_ns_per_query))
+                           float(sim_ns_per_query), int(merge_queries), int(small_queries))
         h = C.c_void_p()
         _check(L.abx_server_create(C.byref(cfg), C.byref(h)), "abx_server_create")
         self._h = h

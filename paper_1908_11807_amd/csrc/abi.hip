@@ -34,7 +34,11 @@ abx_status launch_agglo(bool wide, int kind, bool q16, const void *keys, const f
 abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, TreeHeader *hdr,
                            const int32_t *pre, NodeQ16 *dst, hipStream_t s);
 abx_status launch_preorder(const int32_t *parent_int, const int32_t *other_end, int64_t ni,
-                           uint64_t *work, int32_t *pre, hipStream_t s);
+                           uint64_t *work, int32_t *pre, int32_t *depth, hipStream_t s);
+abx_status launch_wide(int kind, const NodeF32 *src, int64_t ni, const int32_t *pre,
+                       const int32_t *depth, int32_t *flag, int32_t *rank, int64_t *d_total,
+                       void *scan_scratch, size_t scan_bytes, TreeHeader *hdr, NodeW *dst,
+                       hipStream_t s);
 // traverse.hip
 abx_status launch_query_codes(const abx_bvh *b, const float *q, int64_t m, int width,
                               uint32_t *codes, hipStream_t s);
@@ -94,9 +98,18 @@ struct BuildLayout {
   size_t nodes_off, leaves_off, tree_total;
   // scratch
   bool preorder;  // Q16 Karras tree renumbered depth-first
+  bool wnodes;    // 4-wide Q16 nodes (collapsed from the binary tree)
   size_t partial, codes, sorted, perm, parent_leaf, parent_int, other_end, flags, frontier,
-      staging, pre, sort, scratch_total;
+      staging, pre, wbuf, sort, scratch_total;
 };
+
+// 4-wide trees: a walk pushes up to three children per level of half as many
+// levels, so the stacks (kMaxDepth entries, 8 of them for the cooperative
+// pass's share of its frontier) bound the binary height at 78
+bool height_fits(int64_t height, bool wide, int max_depth) {
+  const int64_t need = wide ? 3 * ((height + 1) / 2) : height;
+  return need + 8 < max_depth;
+}
 
 int resolve_bits(const abx_build_options *o) { return (o == nullptr || o->morton_bits == 0) ? 21 : o->morton_bits; }
 
@@ -106,7 +119,8 @@ abx_status check_build_args(const abx_primitives *p, const abx_build_options *o)
   if (p->n < 0) return ABX_ERR_INVALID_ARG;
   if (p->n >= kMaxCount) return ABX_ERR_OVERFLOW;
   if (p->n > 0 && !p->data) return ABX_ERR_INVALID_ARG;
-  if (o && o->node_format != ABX_NODES_FP32 && o->node_format != ABX_NODES_Q16)
+  if (o && o->node_format != ABX_NODES_FP32 && o->node_format != ABX_NODES_Q16 &&
+      o->node_format != ABX_NODES_Q16W)
     return ABX_ERR_INVALID_ARG;
   const int bits = resolve_bits(o);
   if (bits != 10 && bits != 21) return ABX_ERR_INVALID_ARG;
@@ -115,8 +129,13 @@ abx_status check_build_args(const abx_primitives *p, const abx_build_options *o)
   if (o && o->node_order != ABX_ORDER_AUTO && o->node_order != ABX_ORDER_BUILD &&
       o->node_order != ABX_ORDER_DEPTH_FIRST)
     return ABX_ERR_INVALID_ARG;
-  if (o && o->node_order == ABX_ORDER_DEPTH_FIRST &&
-      (o->node_format != ABX_NODES_Q16 || o->hierarchy == ABX_HIERARCHY_AGGLOMERATIVE))
+  if (o && o->node_order == ABX_ORDER_DEPTH_FIRST && o->node_format == ABX_NODES_FP32)
+    return ABX_ERR_UNSUPPORTED;
+  if (o && o->node_order == ABX_ORDER_DEPTH_FIRST && o->hierarchy == ABX_HIERARCHY_AGGLOMERATIVE)
+    return ABX_ERR_UNSUPPORTED;
+  // 4-wide nodes: collapsed from the Karras tree, always in depth-first order
+  if (o && o->node_format == ABX_NODES_Q16W &&
+      (o->hierarchy == ABX_HIERARCHY_AGGLOMERATIVE || o->node_order == ABX_ORDER_BUILD))
     return ABX_ERR_UNSUPPORTED;
   return ABX_OK;
 }
@@ -131,19 +150,21 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   L.ni = p->n > 1 ? p->n - 1 : 0;
   L.bits = resolve_bits(o);
   L.wide = L.bits > 10;
-  L.q16 = o && o->node_format == ABX_NODES_Q16;
-  L.node_bytes = L.q16 ? sizeof(NodeQ16) : sizeof(NodeF32);
+  L.wnodes = o && o->node_format == ABX_NODES_Q16W;
+  L.q16 = o && (o->node_format == ABX_NODES_Q16 || L.wnodes);  // quantised (binary or 4-wide)
+  L.node_bytes = L.wnodes ? sizeof(NodeW) : (L.q16 ? sizeof(NodeQ16) : sizeof(NodeF32));
   L.boxrec = L.q16 && p->kind == ABX_PRIM_BOXES;
   {
     const bool karras = !(o && o->hierarchy == ABX_HIERARCHY_AGGLOMERATIVE);
     const int order = o ? o->node_order : ABX_ORDER_AUTO;
-    L.preorder = L.q16 && karras &&
+    L.preorder = L.q16 && !L.wnodes && karras &&
                  (order == ABX_ORDER_DEPTH_FIRST || (order == ABX_ORDER_AUTO && L.n >= kDepthFirstMinN));
   }
   L.leaf_bytes = L.boxrec ? 32 : 4;
+  const int64_t node_slots = L.wnodes ? wide_node_cap(L.ni) : L.ni;
   size_t off = sizeof(TreeHeader);
   L.nodes_off = off;
-  off = align_up(off + (size_t)L.ni * L.node_bytes, 256);
+  off = align_up(off + (size_t)node_slots * L.node_bytes, 256);
   L.leaves_off = off;
   off = align_up(off + (size_t)L.n * L.leaf_bytes, 256);
   L.tree_total = off;
@@ -172,7 +193,10 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   L.staging = off;
   off = align_up(off + (L.q16 ? (size_t)L.ni * sizeof(NodeF32) : 0), 256);
   L.pre = off;  // depth-first order: two buffers of 64-bit pointer-jumping words, the index
-  off = align_up(off + (L.preorder ? 2 * (size_t)L.ni * 8 + (size_t)L.ni * 4 : 0), 256);
+  off = align_up(off + (L.preorder || L.wnodes ? 2 * (size_t)L.ni * 8 + (size_t)L.ni * 4 : 0), 256);
+  L.wbuf = off;  // 4-wide nodes: depths, flags, ranks [ni + 1], the scan's total and scratch
+  off = align_up(off + (L.wnodes ? align_up(3 * (size_t)L.ni * 4 + 4, 256) + 256 + scan_scratch_bytes(L.ni)
+                                 : 0), 256);
   L.sort = off;
   off = align_up(off + radix_sort_scratch_bytes(L.n, 3 * L.bits), 256);
   L.scratch_total = off;
@@ -443,13 +467,21 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
       // depth-first order of the Q16 nodes (written by the quantisation);
       // run beside the refit on a second stream it saved 0.04 ms of 0.4 at
       // 1e7 (the two share the GPU), so it stays on the caller's stream
-      if (L.preorder) {
+      if (L.preorder || L.wnodes) {
         uint64_t *work = reinterpret_cast<uint64_t *>(sc + L.pre);
         pre = reinterpret_cast<int32_t *>(work + 2 * L.ni);
-        ABX_TRY(launch_preorder(parent_int, other_end, L.ni, work, pre, s));
+        int32_t *depth = L.wnodes ? reinterpret_cast<int32_t *>(sc + L.wbuf) : nullptr;
+        ABX_TRY(launch_preorder(parent_int, other_end, L.ni, work, pre, depth, s));
+        if (L.wnodes) {
+          int32_t *flag = depth + L.ni, *rank = flag + L.ni;
+          char *tail = sc + L.wbuf + align_up(3 * (size_t)L.ni * 4 + 4, 256);
+          ABX_TRY(launch_wide(kind, fnodes, L.ni, pre, depth, flag, rank,
+                              reinterpret_cast<int64_t *>(tail), tail + 256, scan_scratch_bytes(L.ni),
+                              hdr, reinterpret_cast<NodeW *>(tree + L.nodes_off), s));
+        }
       }
     }
-    if (L.q16)
+    if (L.q16 && !L.wnodes)
       ABX_TRY(launch_quantise(kind, fnodes, L.ni, hdr, pre,
                               reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
   }
@@ -462,18 +494,19 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
   if (h.bad & 8) return ABX_ERR_UNSUPPORTED;  // depth-first order out of range (too deep)
   if ((h.bad & 2) && L.q16) return ABX_ERR_UNSUPPORTED;
   // traversal stacks hold at most height + 8 entries (8 = the cooperative
-  // pass's share of the initial frontier)
-  if (h.height + 8 >= max_tree_depth()) return ABX_ERR_UNSUPPORTED;
+  // pass's share of the initial frontier); 4-wide walks more per level
+  if (!height_fits(h.height, L.wnodes, max_tree_depth())) return ABX_ERR_UNSUPPORTED;
 
   abx_bvh *b = new (std::nothrow) abx_bvh;
   if (!b) return ABX_ERR_INVALID_ARG;
   b->n = n;
   b->kind = kind;
-  b->format = L.q16 ? ABX_NODES_Q16 : ABX_NODES_FP32;
+  b->format = L.wnodes ? ABX_NODES_Q16W : (L.q16 ? ABX_NODES_Q16 : ABX_NODES_FP32);
+  b->nint = L.wnodes ? (n > 1 ? h.node_count : 0) : L.ni;
   b->morton_bits = L.bits;
   b->height = h.height;
   b->hierarchy = agglo ? ABX_HIERARCHY_AGGLOMERATIVE : ABX_HIERARCHY_KARRAS;
-  b->node_order = L.preorder ? ABX_ORDER_DEPTH_FIRST : ABX_ORDER_BUILD;
+  b->node_order = L.preorder || L.wnodes ? ABX_ORDER_DEPTH_FIRST : ABX_ORDER_BUILD;
   b->root = h.root;
   std::memcpy(b->scene, h.scene, sizeof(b->scene));
   std::memcpy(b->q_origin, h.q_origin, sizeof(b->q_origin));
@@ -510,6 +543,7 @@ abx_status abx_bvh_get_layout(const abx_bvh *b, abx_bvh_layout *o) {
   o->leaf_bytes = b->leaf_bytes;
   std::memcpy(o->q16_origin, b->q_origin, sizeof(o->q16_origin));
   std::memcpy(o->q16_scale, b->q_scale, sizeof(o->q16_scale));
+  o->node_count = b->nint;
   return ABX_OK;
 }
 

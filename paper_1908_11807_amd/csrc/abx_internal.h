@@ -35,7 +35,8 @@ struct TreeHeader {
                       // kBadSort: the sort's look-back gave up (hierarchy and refit skipped)
   int32_t height;     // longest root-to-leaf path (edges)
   int32_t root;       // internal node at the root (0 for the Karras numbering)
-  int32_t pad[46];
+  int32_t node_count; // internal nodes stored (4-wide trees: fewer than n - 1)
+  int32_t pad[45];
 };
 static_assert(sizeof(TreeHeader) == 256, "header is 256 B");
 constexpr int32_t kBadSort = 16;
@@ -61,6 +62,22 @@ struct __align__(16) NodeQ16 {
 static_assert(sizeof(NodeQ16) == 32, "q16 node is 32 B");
 
 constexpr int kQ16Max = 65535;
+
+// 4-wide Q16 node, 64 B: up to four children, each a 12-byte slot laid out
+// like a Q16 child (6 uint16 coordinates, or a point leaf's float32 x y z),
+// then the four references (kEmptyRef for an unused slot).  A 4-wide tree is
+// the binary tree collapsed at even depths: a node at even depth keeps its
+// children's children (a leaf child stays a leaf child), so a walk takes one
+// dependent node load where the binary tree takes two.
+struct __align__(16) NodeW {
+  uint4 a, b, c, d;  // a..c: slots 0-3 (3 words each), d: references 0-3
+};
+static_assert(sizeof(NodeW) == 64, "4-wide node is 64 B");
+constexpr int32_t kEmptyRef = INT32_MIN;  // never ~i for a primitive i < 2^31 - 1
+// upper bound of the 4-wide nodes of ni binary internal nodes: every node at
+// even depth but the root has a parent at odd depth, which has two children,
+// so W - 1 <= 2 (ni - W)
+inline int64_t wide_node_cap(int64_t ni) { return ni > 0 ? (2 * ni + 1) / 3 + 1 : 0; }
 
 // Walk state a nearest query takes from the one-lane pass to the cooperative
 // pass (int32 words per saved query): entry count (-1: restart from the
@@ -208,6 +225,7 @@ struct abx_bvh {
   int32_t kind, format, morton_bits, height;
   int32_t hierarchy, root;  // construction used; internal node at the root
   int32_t node_order;       // abx_node_order: BUILD or DEPTH_FIRST
+  int64_t nint;             // internal nodes stored (n - 1, fewer for 4-wide nodes)
   float scene[6];
   float q_origin[3], q_scale[3];
   char *tree;  // device base

@@ -137,6 +137,7 @@ __global__ void k_header_init(TreeHeader *hdr) {
     hdr->bad = 0;
     hdr->height = 0;
     hdr->root = 0;  // Karras numbering; the agglomerative build overwrites it
+    hdr->node_count = 0;  // set by the 4-wide emission (binary trees: n - 1)
   }
 }
 
@@ -762,7 +763,9 @@ __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restr
 // to 128 edges; trees are at most ~95 deep).
 constexpr int kPreRounds = 7;
 
-// one 64-bit word per node: left turns counted so far (high half) and the
+// one 64-bit word per node: two counts summed along the path so far in the
+// high half -- left turns (bits 0-15) and edges, i.e. the depth (bits 16-31;
+// both stay below 128, so neither carries into the other) -- and the
 // ancestor to add next (low half, -1 when the root has been passed), so a
 // round gathers one word per node
 __global__ __launch_bounds__(kBuildBlock) void k_pre_init(const int32_t *__restrict__ parent_int,
@@ -770,7 +773,8 @@ __global__ __launch_bounds__(kBuildBlock) void k_pre_init(const int32_t *__restr
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ni) return;
   const int32_t pp = i == 0 ? -1 : parent_int[i];
-  const uint32_t val = pp >= 0 && (pp & 1) == 0 ? 1u : 0u;  // a left child
+  const uint32_t left = pp >= 0 && (pp & 1) == 0 ? 1u : 0u;  // a left child
+  const uint32_t val = pp >= 0 ? left | (1u << 16) : 0u;
   const int32_t anc = pp >= 0 ? pp >> 1 : -1;
   w[i] = ((uint64_t)val << 32) | (uint32_t)anc;
 }
@@ -790,10 +794,12 @@ __global__ __launch_bounds__(kBuildBlock) void k_pre_jump(const uint64_t *__rest
 }
 
 // the last round: the finished count gives the index, first leaf of the
-// node's range + left turns (-1 if the path was longer than the rounds)
+// node's range + left turns (-1 if the path was longer than the rounds), and
+// the depth when asked for
 __global__ __launch_bounds__(kBuildBlock) void k_pre_last(const uint64_t *__restrict__ in, int64_t ni,
                                                           const int32_t *__restrict__ other_end,
-                                                          int32_t *__restrict__ pre) {
+                                                          int32_t *__restrict__ pre,
+                                                          int32_t *__restrict__ depth) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ni) return;
   const uint64_t x = in[i];
@@ -806,12 +812,13 @@ __global__ __launch_bounds__(kBuildBlock) void k_pre_last(const uint64_t *__rest
     rest = (int32_t)(uint32_t)y;
   }
   const int64_t j = other_end[i];
-  pre[i] = rest >= 0 ? -1 : (int32_t)((i < j ? i : j) + (int64_t)v);
+  pre[i] = rest >= 0 ? -1 : (int32_t)((i < j ? i : j) + (int64_t)(v & 0xffffu));
+  if (depth) depth[i] = rest >= 0 ? -1 : (int32_t)((v >> 16) & 0xffffu);
 }
 
-// scratch: 2 * ni words + ni int32 for the result
+// scratch: 2 * ni words + ni int32 for the result (and ni for the depths)
 abx_status launch_preorder(const int32_t *parent_int, const int32_t *other_end, int64_t ni,
-                           uint64_t *work, int32_t *pre, hipStream_t s) {
+                           uint64_t *work, int32_t *pre, int32_t *depth, hipStream_t s) {
   if (ni <= 0) return ABX_OK;
   const unsigned g = grid_for(ni, kBuildBlock);
   uint64_t *buf[2] = {work, work + ni};
@@ -822,7 +829,152 @@ abx_status launch_preorder(const int32_t *parent_int, const int32_t *other_end, 
   }
   const int f = (kPreRounds - 1) & 1;
   return launch("preorder", s, [&] {
-    k_pre_last<<<g, kBuildBlock, 0, s>>>(buf[f], ni, other_end, pre);
+    k_pre_last<<<g, kBuildBlock, 0, s>>>(buf[f], ni, other_end, pre, depth);
+  });
+}
+
+// ------------------------------------------------------ 4-wide Q16 nodes
+// Which binary nodes become 4-wide nodes: those at even depth, flagged at
+// their depth-first position.  A scan of the flags then numbers the 4-wide
+// nodes in depth-first order of the 4-wide tree (a binary node's left
+// subtree precedes its right one, so the even-depth nodes keep that order).
+__global__ __launch_bounds__(kBuildBlock) void k_wide_flags(const int32_t *__restrict__ pre,
+                                                            const int32_t *__restrict__ depth,
+                                                            int64_t ni, int32_t *__restrict__ flag,
+                                                            TreeHeader *__restrict__ hdr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ni || (hdr->bad & kBadSort)) return;
+  const int32_t p = pre[i], d = depth[i];
+  if (p < 0 || p >= ni || d < 0) {
+    atomicOr(&hdr->bad, 8);
+    return;
+  }
+  flag[p] = (d & 1) == 0 ? 1 : 0;
+}
+
+// One thread per binary node at even depth: gather its grandchildren (a leaf
+// child is kept as it is), quantise their boxes outward on the scene grid as
+// k_quantise does (point leaves keep their float32 coordinates) and write the
+// 4-wide node to its depth-first slot widx = rank[pre[i]].
+template <int KIND>
+__global__ __launch_bounds__(kBuildBlock) void k_wide_emit(const NodeF32 *__restrict__ src, int64_t ni,
+                                                           const int32_t *__restrict__ pre,
+                                                           const int32_t *__restrict__ depth,
+                                                           const int32_t *__restrict__ rank,
+                                                           TreeHeader *__restrict__ hdr,
+                                                           NodeW *__restrict__ dst, int64_t cap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ni || (hdr->bad & (4 | 8 | kBadSort))) return;
+  if (i == 0) {
+    const int32_t total = rank[ni];
+    hdr->node_count = total;
+    if (total < 1 || total > cap) atomicOr(&hdr->bad, 8);
+  }
+  if (depth[i] & 1) return;  // odd depth: folded into its parent
+  const int64_t w = rank[pre[i]];
+  if (w < 0 || w >= cap) {
+    atomicOr(&hdr->bad, 8);
+    return;
+  }
+  float o[3], sc[3], inv[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    o[a] = hdr->q_origin[a];
+    sc[a] = hdr->q_scale[a];
+    inv[a] = sc[a] != 0.0f ? 1.0f / sc[a] : 0.0f;
+  }
+  // Slots, without run-time indexing: a binary child that is a leaf gives
+  // one slot (its own box), an internal one its two children.  With A0 A1
+  // from the left child and B0 B1 from the right (A1, B1 only when that
+  // child is internal) the slots are A0, then A1 if present, then B0, B1.
+  const int4 d = src[i].d;
+  const float *f = reinterpret_cast<const float *>(src + i);
+  const bool ai = d.x >= 0, bi = d.y >= 0;
+  if ((ai && d.x >= ni) || (bi && d.y >= ni)) {
+    atomicOr(&hdr->bad, 8);
+    return;
+  }
+  const float *ga = ai ? reinterpret_cast<const float *>(src + d.x) : f;
+  const float *gb = bi ? reinterpret_cast<const float *>(src + d.y) : f;
+  const int4 da = ai ? src[d.x].d : make_int4(0, 0, 0, 0);
+  const int4 db = bi ? src[d.y].d : make_int4(0, 0, 0, 0);
+  // 4-wide numbers of internal grandchildren
+  auto wide_ref = [&](int32_t g, bool &ok) -> int32_t {
+    if (g < 0) return g;
+    if (g >= ni || pre[g] < 0 || pre[g] >= ni) {
+      ok = false;
+      return kEmptyRef;
+    }
+    return rank[pre[g]];
+  };
+  bool ok = true;
+  const int32_t ra0 = ai ? wide_ref(da.x, ok) : d.x, ra1 = ai ? wide_ref(da.y, ok) : kEmptyRef;
+  const int32_t rb0 = bi ? wide_ref(db.x, ok) : d.y, rb1 = bi ? wide_ref(db.y, ok) : kEmptyRef;
+  if (!ok) {
+    atomicOr(&hdr->bad, 8);
+    return;
+  }
+  // A0 = left leaf or its first child, A1 its second child; B0, B1 the same
+  // on the right
+  const float *pa0 = ai ? ga : f, *pa1 = ga + 6, *pb0 = bi ? gb : f + 6, *pb1 = gb + 6;
+  // the slots, by selects only: A0, then A1 if present, then B0, then B1
+  // if present
+  const float *ps[4] = {pa0, ai ? pa1 : pb0, ai ? pb0 : pb1, pb1};
+  const int32_t rs[4] = {ra0, ai ? ra1 : rb0, ai ? rb0 : (bi ? rb1 : kEmptyRef), ai && bi ? rb1 : kEmptyRef};
+  const bool used[4] = {true, true, ai || bi, ai && bi};
+  float box[4][6];
+  int32_t ref[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) box[c][e] = used[c] ? ps[c][e] : 0.0f;
+    ref[c] = rs[c];
+  }
+  uint32_t wd[12];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (!used[c]) {
+      wd[3 * c] = wd[3 * c + 1] = wd[3 * c + 2] = 0u;
+    } else if (KIND == ABX_PRIM_POINTS && ref[c] < 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wd[3 * c + a] = __float_as_uint(box[c][a]);
+    } else {
+      uint32_t q[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        q[a] = q_lo(box[c][a], o[a], sc[a], inv[a]);
+        q[3 + a] = q_hi(box[c][3 + a], o[a], sc[a], inv[a]);
+      }
+#pragma unroll
+      for (int h = 0; h < 3; ++h) wd[3 * c + h] = q[2 * h] | (q[2 * h + 1] << 16);
+    }
+  }
+  NodeW out;
+  out.a = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+  out.b = make_uint4(wd[4], wd[5], wd[6], wd[7]);
+  out.c = make_uint4(wd[8], wd[9], wd[10], wd[11]);
+  out.d = make_uint4((uint32_t)ref[0], (uint32_t)ref[1], (uint32_t)ref[2], (uint32_t)ref[3]);
+  dst[w] = out;
+}
+
+// flags [ni], rank [ni + 1] (exclusive scan of the flags), scan scratch
+abx_status launch_wide(int kind, const NodeF32 *src, int64_t ni, const int32_t *pre,
+                       const int32_t *depth, int32_t *flag, int32_t *rank, int64_t *d_total,
+                       void *scan_scratch, size_t scan_bytes, TreeHeader *hdr, NodeW *dst,
+                       hipStream_t s) {
+  if (ni <= 0) return ABX_OK;
+  const unsigned g = grid_for(ni, kBuildBlock);
+  ABX_TRY(launch("wide_flags", s, [&] {
+    k_wide_flags<<<g, kBuildBlock, 0, s>>>(pre, depth, ni, flag, hdr);
+  }));
+  ABX_TRY(exclusive_scan(flag, ni, rank, d_total, scan_scratch, scan_bytes, s));
+  const int64_t cap = wide_node_cap(ni);
+  if (kind == ABX_PRIM_POINTS)
+    return launch("wide_emit", s, [&] {
+      k_wide_emit<ABX_PRIM_POINTS><<<g, kBuildBlock, 0, s>>>(src, ni, pre, depth, rank, hdr, dst, cap);
+    });
+  return launch("wide_emit", s, [&] {
+    k_wide_emit<ABX_PRIM_BOXES><<<g, kBuildBlock, 0, s>>>(src, ni, pre, depth, rank, hdr, dst, cap);
   });
 }
 

@@ -145,6 +145,7 @@ abx_status check_offsets(const int64_t *off, int T) {
 
 abx_status check_forest_prims(const abx_forest_primitives *p) {
   if (!p || p->trees < 1 || p->trees > forest_max_trees()) return ABX_ERR_INVALID_ARG;
+  if (p->node_format == ABX_NODES_Q16W) return ABX_ERR_UNSUPPORTED;  // binary nodes only
   if (p->node_format != ABX_NODES_FP32 && p->node_format != ABX_NODES_Q16) return ABX_ERR_INVALID_ARG;
   ABX_TRY(check_offsets(p->offsets_host, p->trees));
   if (!p->offsets_dev || (p->offsets_host[p->trees] > 0 && !p->data)) return ABX_ERR_INVALID_ARG;
@@ -178,6 +179,7 @@ TreeArgs forest_tree_args(const abx_forest *f) {
   t.nodes = f->tree + f->L.nodes;
   t.leaves = f->tree + f->L.leaves;
   t.n = f->N;
+  t.nint = f->N > 1 ? f->N - 1 : 0;
   t.scene_dev = hdr->scene;
   t.qframe = hdr->q_origin;  // q_origin[3] then q_scale[3]
   t.guard = hdr;             // the query exits if the construction failed

@@ -111,33 +111,51 @@ struct Block {
 
 enum Phase { P_QUEUED, P_RUN_A, P_WAIT_FILL, P_RUN_B, P_DONE };
 
+struct Batch;
+
 struct Req {
   uint64_t ticket;
   abx_request r;
   Phase phase = P_QUEUED;
-  int slot = -1;
+  Batch *batch = nullptr;
   int64_t kk = 0, total = 0;
+  int64_t base = 0;           // first row of the request in its batch
+  int64_t row0 = 0;           // radius: the batch offset at `base` (its first result)
   abx_status status = ABX_OK;
-  double t_admit = 0, t_done = 0, sim_deadline = 0;
-  double t_device = 0;        // summed GPU time of the request's phases
-  Block dev_a, dev_b, host;   // device: phase A / fill reservation; host: results
-  // carved device pointers
+  double t_admit = 0, t_done = 0;
+  double t_device = 0;        // summed GPU time of the phases of its batch
+  Block host;                 // results, pinned host arena
+  int32_t *h_off = nullptr, *h_idx = nullptr;
+  float *h_dist = nullptr;
+};
+
+// Requests on one tree with the same predicate (kind and k, or radius) run
+// as one launch sequence over their concatenated queries.  Each row's result
+// depends only on its own query, so a request's rows are the same alone or
+// merged (results are copied back per request).
+struct Batch {
+  std::vector<Req *> reqs;
+  int32_t tree = 0;
+  abx_request_kind kind = ABX_REQ_NEAREST;
+  int32_t k = 0;
+  float radius = 0.0f;
+  int64_t kk = 0, M = 0, total = 0;
+  bool large = false;
+  Phase phase = P_RUN_A;
+  int slot = -1;
+  Block dev_a, dev_b;
+  double sim_deadline = 0;
   float *d_q = nullptr;
   char *d_scratch = nullptr;
   int32_t *d_off = nullptr, *d_idx = nullptr;
   float *d_dist = nullptr;
-  int64_t *d_total = nullptr;
-  // carved host pointers (pinned arena)
-  int32_t *h_off = nullptr, *h_idx = nullptr;
-  float *h_dist = nullptr;
-  int64_t *h_total = nullptr;
 };
 
 struct Slot {
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;        // completion (polled)
   hipEvent_t t0 = nullptr, t1 = nullptr;  // timing: start and end of a phase
-  Req *r = nullptr;
+  Batch *b = nullptr;
 };
 
 }  // namespace
@@ -145,6 +163,7 @@ struct Slot {
 struct abx_server {
   abx_server_config cfg;
   int device = 0;
+  int64_t merge_queries = 0, small_queries = 0;  // resolved merge limits (0: no merging)
   std::vector<const abx_bvh *> trees;
   std::vector<Slot> slots;
   Arena dev, host;
@@ -162,22 +181,42 @@ struct abx_server {
 
 namespace {
 
-size_t request_scratch_bytes(const Req *q) {
-  return q->r.kind == ABX_REQ_NEAREST ? nearest_scratch_bytes(q->r.m) : query_scratch_bytes(q->r.m);
+constexpr int kMaxBatchRequests = 64;
+
+bool same_class(const Req *a, const Req *b) {
+  if (a->r.tree != b->r.tree || a->r.kind != b->r.kind) return false;
+  if (a->r.kind == ABX_REQ_NEAREST) return a->kk == b->kk;
+  return std::memcmp(&a->r.radius, &b->r.radius, sizeof(float)) == 0;
 }
 
-size_t dev_bytes_a(const abx_server *S, const Req *q) {
-  const int64_t m = q->r.m;
-  size_t b = align_up((size_t)m * 12, kGrain) + align_up(request_scratch_bytes(q), kGrain);
-  if (q->r.kind == ABX_REQ_NEAREST) b += 2 * align_up((size_t)(m * q->kk) * 4, kGrain);
-  else b += align_up((size_t)(m + 1) * 4, kGrain);
-  (void)S;
-  return b;
+bool is_large(const abx_server *S, const Req *q) { return q->r.m > S->small_queries; }
+
+// Query ordering per batch.  At request sizes (up to ~1e5 queries) the
+// ordering's sort costs 60-90 us, measured against 1e7-point trees: radius
+// requests never win it back (their walks are short), nearest requests do
+// from ~1e4 queries where walks are long (a shell: 3.5 vs 4.4 ms at 1e4
+// queries, k = 8), and lose it below.
+constexpr int64_t kServeSortMin = 4096;
+int sort_batch(const Batch *b) { return b->kind == ABX_REQ_NEAREST && b->M >= kServeSortMin ? 1 : 0; }
+
+size_t batch_scratch_bytes(const Batch *b) {
+  return b->kind == ABX_REQ_NEAREST ? nearest_scratch_bytes(b->M) : query_scratch_bytes(b->M);
 }
 
+// device reservation of a batch's first phase: queries, query scratch and
+// the nearest results or the radius offsets
+size_t dev_bytes_a(const Batch *b) {
+  const int64_t M = b->M;
+  size_t n = align_up((size_t)M * 12, kGrain) + align_up(batch_scratch_bytes(b), kGrain);
+  if (b->kind == ABX_REQ_NEAREST) n += 2 * align_up((size_t)(M * b->kk) * 4, kGrain);
+  else n += align_up((size_t)(M + 1) * 4, kGrain);
+  return n;
+}
+
+// host reservation of one request's first phase: offsets (+ nearest results)
 size_t host_bytes_a(const Req *q) {
   const int64_t m = q->r.m;
-  size_t b = align_up((size_t)(m + 1) * 4, kGrain) + kGrain;  // offsets + total
+  size_t b = align_up((size_t)(m + 1) * 4, kGrain) + kGrain;
   if (q->r.kind == ABX_REQ_NEAREST) b += 2 * align_up((size_t)(m * q->kk) * 4, kGrain);
   return b;
 }
@@ -202,11 +241,8 @@ void finish(abx_server *S, Req *q, abx_status status) {
   q->status = status;
   q->phase = P_DONE;
   q->t_done = now_s();
-  release_block(S->dev, q->dev_a);
-  release_block(S->dev, q->dev_b);
+  q->batch = nullptr;
   if (status != ABX_OK) release_block(S->host, q->host);
-  if (q->slot >= 0) S->slots[q->slot].r = nullptr;
-  q->slot = -1;
   S->in_flight--;
   if (status == ABX_OK) {
     S->st.completed++;
@@ -217,241 +253,435 @@ void finish(abx_server *S, Req *q, abx_status status) {
   S->cv_done.notify_all();
 }
 
-// Query ordering per request.  At request sizes (up to ~1e5 queries) the
-// ordering's sort costs 60-90 us, measured against 1e7-point trees: radius
-// requests never win it back (their walks are short), nearest requests do
-// from ~1e4 queries where walks are long (a shell: 3.5 vs 4.4 ms at 1e4
-// queries, k = 8), and lose it below.
-constexpr int64_t kServeSortMin = 4096;
-int sort_request(const Req *q) {
-  return q->r.kind == ABX_REQ_NEAREST && q->r.m >= kServeSortMin ? 1 : 0;
+// ends a batch: every member finishes with `status` (OK: its results are
+// in place), the batch's memory and slot are released
+void finish_batch(abx_server *S, Batch *b, abx_status status) {
+  for (Req *q : b->reqs) finish(S, q, status);
+  release_block(S->dev, b->dev_a);
+  release_block(S->dev, b->dev_b);
+  if (b->slot >= 0) S->slots[b->slot].b = nullptr;
+  delete b;
 }
 
-// host-side offsets of a nearest request: row i starts at i * k'
-void nearest_offsets(Req *q) {
-  if (!q->h_off) return;
-  for (int64_t i = 0; i <= q->r.m; ++i) q->h_off[i] = (int32_t)(i * q->kk);
-}
-
-abx_status launch_a(abx_server *S, Req *q) {
-  const abx_bvh *tree = S->trees[q->r.tree];
-  const int64_t m = q->r.m;
-  Slot &sl = S->slots[q->slot];
-  char *d = S->dev_base + q->dev_a.off;
-  char *h = S->host_base + q->host.off;
-  q->d_q = reinterpret_cast<float *>(d);
-  d += align_up((size_t)m * 12, kGrain);
-  q->d_scratch = d;
-  d += align_up(request_scratch_bytes(q), kGrain);
-  q->h_off = reinterpret_cast<int32_t *>(h);
-  h += align_up((size_t)(m + 1) * 4, kGrain);
-  q->h_total = reinterpret_cast<int64_t *>(h);
-  h += kGrain;
-  if (q->r.kind == ABX_REQ_NEAREST) {
-    q->d_idx = reinterpret_cast<int32_t *>(d);
-    d += align_up((size_t)(m * q->kk) * 4, kGrain);
-    q->d_dist = reinterpret_cast<float *>(d);
-    q->h_idx = reinterpret_cast<int32_t *>(h);
-    h += align_up((size_t)(m * q->kk) * 4, kGrain);
-    q->h_dist = reinterpret_cast<float *>(h);
+abx_status launch_a(abx_server *S, Batch *b) {
+  const abx_bvh *tree = S->trees[b->tree];
+  const int64_t M = b->M;
+  char *d = S->dev_base + b->dev_a.off;
+  b->d_q = reinterpret_cast<float *>(d);
+  d += align_up((size_t)M * 12, kGrain);
+  b->d_scratch = d;
+  d += align_up(batch_scratch_bytes(b), kGrain);
+  if (b->kind == ABX_REQ_NEAREST) {
+    b->d_idx = reinterpret_cast<int32_t *>(d);
+    d += align_up((size_t)(M * b->kk) * 4, kGrain);
+    b->d_dist = reinterpret_cast<float *>(d);
   } else {
-    q->d_off = reinterpret_cast<int32_t *>(d);
+    b->d_off = reinterpret_cast<int32_t *>(d);
+  }
+  for (Req *q : b->reqs) {
+    char *h = S->host_base + q->host.off;
+    q->h_off = reinterpret_cast<int32_t *>(h);
+    h += align_up((size_t)(q->r.m + 1) * 4, kGrain) + kGrain;
+    if (b->kind == ABX_REQ_NEAREST) {
+      q->h_idx = reinterpret_cast<int32_t *>(h);
+      h += align_up((size_t)(q->r.m * q->kk) * 4, kGrain);
+      q->h_dist = reinterpret_cast<float *>(h);
+    }
   }
   if (S->cfg.simulate) {
-    q->sim_deadline = now_s() + 1e-9 * S->cfg.sim_ns_per_query * (double)(m > 0 ? m : 1);
+    b->sim_deadline = now_s() + 1e-9 * S->cfg.sim_ns_per_query * (double)(M > 0 ? M : 1);
     return ABX_OK;
   }
+  Slot &sl = S->slots[b->slot];
   ABX_HIP(hipEventRecord(sl.t0, sl.s));
-  if (m > 0) ABX_HIP(hipMemcpyAsync(q->d_q, q->r.queries, (size_t)m * 12, hipMemcpyHostToDevice, sl.s));
-  if (q->r.kind == ABX_REQ_NEAREST) {
-    ABX_TRY(nearest_enqueue(tree, q->d_q, m, q->r.k, sort_request(q), q->d_scratch, nullptr, q->d_idx,
-                            q->d_dist, sl.s));
-    const size_t ob = (size_t)(m * q->kk) * 4;
-    if (ob) {
-      ABX_HIP(hipMemcpyAsync(q->h_idx, q->d_idx, ob, hipMemcpyDeviceToHost, sl.s));
-      ABX_HIP(hipMemcpyAsync(q->h_dist, q->d_dist, ob, hipMemcpyDeviceToHost, sl.s));
+  for (Req *q : b->reqs)
+    if (q->r.m > 0)
+      ABX_HIP(hipMemcpyAsync(b->d_q + 3 * q->base, q->r.queries, (size_t)q->r.m * 12,
+                             hipMemcpyHostToDevice, sl.s));
+  if (b->kind == ABX_REQ_NEAREST) {
+    ABX_TRY(nearest_enqueue(tree, b->d_q, M, b->k, sort_batch(b), b->d_scratch, nullptr, b->d_idx,
+                            b->d_dist, sl.s));
+    for (Req *q : b->reqs) {
+      const size_t ob = (size_t)(q->r.m * b->kk) * 4;
+      if (!ob) continue;
+      ABX_HIP(hipMemcpyAsync(q->h_idx, b->d_idx + q->base * b->kk, ob, hipMemcpyDeviceToHost, sl.s));
+      ABX_HIP(hipMemcpyAsync(q->h_dist, b->d_dist + q->base * b->kk, ob, hipMemcpyDeviceToHost, sl.s));
     }
   } else {
-    abx_predicates p{ABX_PRED_WITHIN, q->d_q, m, nullptr, q->r.radius, sort_request(q)};
-    ABX_TRY(spatial_count_enqueue(tree, &p, q->d_scratch, q->d_off, &q->d_total, sl.s));
-    ABX_HIP(hipMemcpyAsync(q->h_total, q->d_total, 8, hipMemcpyDeviceToHost, sl.s));
+    abx_predicates p{ABX_PRED_WITHIN, b->d_q, M, nullptr, b->radius, sort_batch(b)};
+    int64_t *d_total = nullptr;
+    ABX_TRY(spatial_count_enqueue(tree, &p, b->d_scratch, b->d_off, &d_total, sl.s));
+    // each request's slice of the offsets: its row count and first result
+    for (Req *q : b->reqs)
+      ABX_HIP(hipMemcpyAsync(q->h_off, b->d_off + q->base, (size_t)(q->r.m + 1) * 4,
+                             hipMemcpyDeviceToHost, sl.s));
   }
   ABX_HIP(hipEventRecord(sl.t1, sl.s));
   ABX_HIP(hipEventRecord(sl.ev, sl.s));
   return ABX_OK;
 }
 
-// fill phase of a radius request: reserve the exact result space, launch
-bool try_launch_b(abx_server *S, Req *q, abx_status *err) {
-  const int64_t m = q->r.m, t = q->total;
-  const size_t ib = align_up((size_t)t * 4, kGrain);
-  if (!take(S->dev, q->dev_b, ib)) return false;
-  // grow the host block: results (offsets already reserved) + indices
-  Block hb;
-  if (!take(S->host, hb, align_up((size_t)(m + 1) * 4, kGrain) + ib)) {
-    release_block(S->dev, q->dev_b);
-    return false;
+// fill phase of a radius batch: reserve the exact result space (device: the
+// batch's indices; host: each request's offsets and indices), launch
+bool try_launch_b(abx_server *S, Batch *b, abx_status *err) {
+  const size_t ib = align_up((size_t)b->total * 4, kGrain);
+  if (!take(S->dev, b->dev_b, ib)) return false;
+  std::vector<Block> hb(b->reqs.size());
+  for (size_t i = 0; i < b->reqs.size(); ++i) {
+    const Req *q = b->reqs[i];
+    if (!take(S->host, hb[i], align_up((size_t)(q->r.m + 1) * 4, kGrain) + align_up((size_t)q->total * 4, kGrain))) {
+      for (size_t j = 0; j < i; ++j) release_block(S->host, hb[j]);
+      release_block(S->dev, b->dev_b);
+      return false;
+    }
   }
-  release_block(S->host, q->host);
-  q->host = hb;
-  char *h = S->host_base + hb.off;
-  q->h_off = reinterpret_cast<int32_t *>(h);
-  q->h_idx = reinterpret_cast<int32_t *>(h + align_up((size_t)(m + 1) * 4, kGrain));
-  q->h_dist = nullptr;
-  q->d_idx = reinterpret_cast<int32_t *>(S->dev_base + q->dev_b.off);
-  q->phase = P_RUN_B;
+  for (size_t i = 0; i < b->reqs.size(); ++i) {
+    Req *q = b->reqs[i];
+    release_block(S->host, q->host);
+    q->host = hb[i];
+    char *h = S->host_base + q->host.off;
+    q->h_off = reinterpret_cast<int32_t *>(h);
+    q->h_idx = reinterpret_cast<int32_t *>(h + align_up((size_t)(q->r.m + 1) * 4, kGrain));
+    q->h_dist = nullptr;
+    q->phase = P_RUN_B;
+  }
+  b->d_idx = reinterpret_cast<int32_t *>(S->dev_base + b->dev_b.off);
+  b->phase = P_RUN_B;
   if (S->cfg.simulate) {
-    q->sim_deadline = now_s() + 1e-9 * S->cfg.sim_ns_per_query * (double)(m > 0 ? m : 1);
+    b->sim_deadline = now_s() + 1e-9 * S->cfg.sim_ns_per_query * (double)(b->M > 0 ? b->M : 1);
     return true;
   }
-  Slot &sl = S->slots[q->slot];
-  const abx_bvh *tree = S->trees[q->r.tree];
-  abx_predicates p{ABX_PRED_WITHIN, q->d_q, m, nullptr, q->r.radius, sort_request(q)};
-  if (hipEventRecord(sl.t0, sl.s) != hipSuccess) {
-    *err = ABX_ERR_HIP;
-    return true;
+  Slot &sl = S->slots[b->slot];
+  const abx_bvh *tree = S->trees[b->tree];
+  abx_predicates p{ABX_PRED_WITHIN, b->d_q, b->M, nullptr, b->radius, sort_batch(b)};
+  *err = ABX_OK;
+  if (hipEventRecord(sl.t0, sl.s) != hipSuccess) *err = ABX_ERR_HIP;
+  if (*err == ABX_OK) *err = spatial_fill_enqueue(tree, &p, b->d_scratch, b->d_off, b->d_idx, sl.s);
+  for (Req *q : b->reqs) {
+    if (*err != ABX_OK) break;
+    if (hipMemcpyAsync(q->h_off, b->d_off + q->base, (size_t)(q->r.m + 1) * 4, hipMemcpyDeviceToHost,
+                       sl.s) != hipSuccess)
+      *err = ABX_ERR_HIP;
+    if (*err == ABX_OK && q->total > 0 &&
+        hipMemcpyAsync(q->h_idx, b->d_idx + q->row0, (size_t)q->total * 4, hipMemcpyDeviceToHost,
+                       sl.s) != hipSuccess)
+      *err = ABX_ERR_HIP;
   }
-  *err = spatial_fill_enqueue(tree, &p, q->d_scratch, q->d_off, q->d_idx, sl.s);
-  if (*err == ABX_OK && hipMemcpyAsync(q->h_off, q->d_off, (size_t)(m + 1) * 4, hipMemcpyDeviceToHost, sl.s) != hipSuccess)
-    *err = ABX_ERR_HIP;
-  if (*err == ABX_OK && t > 0 &&
-      hipMemcpyAsync(q->h_idx, q->d_idx, (size_t)t * 4, hipMemcpyDeviceToHost, sl.s) != hipSuccess)
-    *err = ABX_ERR_HIP;
   if (*err == ABX_OK && hipEventRecord(sl.t1, sl.s) != hipSuccess) *err = ABX_ERR_HIP;
   if (*err == ABX_OK && hipEventRecord(sl.ev, sl.s) != hipSuccess) *err = ABX_ERR_HIP;
   return true;
 }
 
-bool phase_done(abx_server *S, Req *q) {
-  if (S->cfg.simulate) return now_s() >= q->sim_deadline;
-  const hipError_t e = hipEventQuery(S->slots[q->slot].ev);
+bool phase_done(abx_server *S, const Batch *b) {
+  if (S->cfg.simulate) return now_s() >= b->sim_deadline;
+  const hipError_t e = hipEventQuery(S->slots[b->slot].ev);
   return e != hipErrorNotReady;
+}
+
+// after the count phase: each request's result count from its offset slice
+// (simulated: 10 per query), the batch total; false if it overflows
+bool count_results(abx_server *S, Batch *b) {
+  int64_t T = 0;
+  for (Req *q : b->reqs) {
+    if (S->cfg.simulate) {
+      q->row0 = T;
+      q->total = 10 * q->r.m;
+    } else {
+      q->row0 = q->h_off[0];
+      q->total = (int64_t)q->h_off[q->r.m] - q->h_off[0];
+    }
+    T += q->total;
+  }
+  b->total = T;
+  return T < INT32_MAX;
+}
+
+void complete_batch(abx_server *S, Batch *b) {
+  if (b->kind == ABX_REQ_NEAREST) {
+    for (Req *q : b->reqs)
+      for (int64_t i = 0; i <= q->r.m; ++i) q->h_off[i] = (int32_t)(i * q->kk);
+  } else if (!S->cfg.simulate) {
+    // the offsets of the batch, rebased to each request's first result
+    for (Req *q : b->reqs)
+      for (int64_t i = 0; i <= q->r.m; ++i) q->h_off[i] -= (int32_t)q->row0;
+  }
+  finish_batch(S, b, ABX_OK);
+}
+
+// The batch a request heads: itself, and when it is small, the later queued
+// small requests of its class (in queue order) while the batch stays within
+// the merge limits.  Members leave the queue.
+Batch *form_batch(abx_server *S, std::deque<Req *>::iterator head) {
+  Req *h = *head;
+  Batch *b = new (std::nothrow) Batch;
+  if (!b) return nullptr;
+  b->tree = h->r.tree;
+  b->kind = h->r.kind;
+  b->k = h->r.k;
+  b->radius = h->r.radius;
+  b->kk = h->kk;
+  b->large = is_large(S, h);
+  b->reqs.push_back(h);
+  b->M = h->r.m;
+  auto it = S->queue.erase(head);
+  if (!b->large && S->merge_queries > 0) {
+    while (it != S->queue.end() && (int)b->reqs.size() < kMaxBatchRequests) {
+      Req *q = *it;
+      if (!is_large(S, q) && same_class(h, q) && b->M + q->r.m <= S->merge_queries) {
+        q->base = b->M;
+        b->M += q->r.m;
+        b->reqs.push_back(q);
+        it = S->queue.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  h->base = 0;
+  return b;
+}
+
+// the queue in submission order (after requests went back to it)
+void sort_queue(abx_server *S) {
+  std::sort(S->queue.begin(), S->queue.end(), [](const Req *x, const Req *y) { return x->ticket < y->ticket; });
+}
+
+// returns a batch's requests to the queue, at their places by ticket
+void requeue_batch(abx_server *S, Batch *b) {
+  for (Req *q : b->reqs) {
+    release_block(S->host, q->host);
+    q->phase = P_QUEUED;
+    q->batch = nullptr;
+    q->total = 0;
+    q->base = 0;
+    S->in_flight--;
+    S->st.requeued++;
+    S->queue.push_back(q);
+  }
+  sort_queue(S);
+  release_block(S->dev, b->dev_a);
+  release_block(S->dev, b->dev_b);
+  if (b->slot >= 0) S->slots[b->slot].b = nullptr;
+  delete b;
+}
+
+// admits the batch headed by *head on slot `slot`: reserves its memory,
+// launches its first phase; false (nothing changed) if the memory is not
+// there
+bool admit(abx_server *S, std::deque<Req *>::iterator head, int slot) {
+  Req *h = *head;
+  // a request that can never fit fails at once
+  {
+    Batch probe;
+    probe.kind = h->r.kind;
+    probe.kk = h->kk;
+    probe.M = h->r.m;
+    if (dev_bytes_a(&probe) > S->dev.size() || host_bytes_a(h) > S->host.size()) {
+      S->queue.erase(head);
+      S->in_flight++;
+      finish(S, h, ABX_ERR_CAPACITY);
+      return true;
+    }
+  }
+  Batch *b = form_batch(S, head);
+  if (!b) return false;
+  // memory for the batch; members whose host space is not there go back
+  bool ok = take(S->dev, b->dev_a, dev_bytes_a(b));
+  std::vector<Req *> back;
+  if (ok) {
+    for (size_t i = 0; i < b->reqs.size(); ++i) {
+      Req *q = b->reqs[i];
+      if (!take(S->host, q->host, host_bytes_a(q))) {
+        if (i == 0) ok = false;
+        back.assign(b->reqs.begin() + (ptrdiff_t)i, b->reqs.end());
+        b->reqs.resize(i);
+        break;
+      }
+    }
+  }
+  if (!ok) {
+    // nothing admitted: the requests return to their places at the front
+    release_block(S->dev, b->dev_a);
+    for (Req *q : b->reqs) release_block(S->host, q->host);
+    for (Req *q : b->reqs) S->queue.push_back(q);
+    for (Req *q : back) S->queue.push_back(q);
+    sort_queue(S);
+    delete b;
+    return false;
+  }
+  if (!back.empty()) {
+    // shrink the batch to the members that got host space; the rest requeue
+    for (Req *q : back) S->queue.push_back(q);
+    sort_queue(S);
+    int64_t M = 0;
+    for (Req *q : b->reqs) {
+      q->base = M;
+      M += q->r.m;
+    }
+    release_block(S->dev, b->dev_a);
+    b->M = M;
+    if (!take(S->dev, b->dev_a, dev_bytes_a(b))) {  // cannot happen: it shrank
+      for (Req *q : b->reqs) {
+        release_block(S->host, q->host);
+        S->queue.push_back(q);
+      }
+      sort_queue(S);
+      delete b;
+      return false;
+    }
+  }
+  const double t = now_s();
+  b->slot = slot;
+  b->phase = P_RUN_A;
+  S->slots[slot].b = b;
+  for (Req *q : b->reqs) {
+    q->phase = P_RUN_A;
+    q->batch = b;
+    q->t_admit = t;
+    S->in_flight++;
+  }
+  S->st.max_in_flight = std::max<int64_t>(S->st.max_in_flight, S->in_flight);
+  S->st.batches++;
+  const abx_status e = launch_a(S, b);
+  if (e != ABX_OK) finish_batch(S, b, e);
+  return true;
 }
 
 // one pass of the scheduler; returns true if anything changed
 bool step(abx_server *S) {
   bool changed = false;
-  bool fill_waiting = false;
+  size_t fill_need = 0;  // device bytes a waiting fill needs; admission leaves them free
   // 1. completions
   for (auto &sl : S->slots) {
-    Req *q = sl.r;
-    if (!q) continue;
-    if (q->phase == P_WAIT_FILL) {
+    Batch *b = sl.b;
+    if (!b) continue;
+    if (b->phase == P_WAIT_FILL) {
       abx_status err = ABX_OK;
-      if (try_launch_b(S, q, &err)) {
+      if (try_launch_b(S, b, &err)) {
         changed = true;
-        if (err != ABX_OK) finish(S, q, err);
-      } else if (S->dev.used() == q->dev_a.bytes && S->host.used() == q->host.bytes) {
-        // alone in both arenas and the result space still does not fit (results
-        // that the caller has not released yet hold host space: wait for them)
-        finish(S, q, ABX_ERR_CAPACITY);
-        changed = true;
+        if (err != ABX_OK) finish_batch(S, b, err);
       } else {
-        fill_waiting = true;
+        size_t hold = 0;
+        for (Req *q : b->reqs) hold += q->host.bytes;
+        if (S->dev.used() == b->dev_a.bytes && S->host.used() == hold) {
+          // alone in both arenas and the result space still does not fit
+          // (results the caller has not released hold host space: wait)
+          finish_batch(S, b, ABX_ERR_CAPACITY);
+          changed = true;
+        } else {
+          fill_need = std::max(fill_need, align_up((size_t)b->total * 4, kGrain));
+        }
       }
       continue;
     }
-    if (!phase_done(S, q)) continue;
+    if (!phase_done(S, b)) continue;
     changed = true;
     if (!S->cfg.simulate && hipEventQuery(sl.ev) != hipSuccess) {
-      finish(S, q, ABX_ERR_HIP);
+      finish_batch(S, b, ABX_ERR_HIP);
       continue;
     }
+    double dt = 0.0;
     if (S->cfg.simulate) {
-      q->t_device += 1e-9 * S->cfg.sim_ns_per_query * (double)(q->r.m > 0 ? q->r.m : 1);
+      dt = 1e-9 * S->cfg.sim_ns_per_query * (double)(b->M > 0 ? b->M : 1);
     } else {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, sl.t0, sl.t1) == hipSuccess) q->t_device += 1e-3 * (double)ms;
+      if (hipEventElapsedTime(&ms, sl.t0, sl.t1) == hipSuccess) dt = 1e-3 * (double)ms;
     }
-    if (q->phase == P_RUN_A && q->r.kind == ABX_REQ_RADIUS) {
-      q->total = S->cfg.simulate ? 10 * q->r.m : *q->h_total;
-      if (q->total >= INT32_MAX) {
-        finish(S, q, ABX_ERR_OVERFLOW);
+    for (Req *q : b->reqs) q->t_device += dt;
+    if (b->phase == P_RUN_A && b->kind == ABX_REQ_RADIUS) {
+      if (!count_results(S, b)) {
+        finish_batch(S, b, ABX_ERR_OVERFLOW);
         continue;
       }
-      release_block(S->dev, q->dev_b);
       abx_status err = ABX_OK;
-      if (!try_launch_b(S, q, &err)) {
-        q->phase = P_WAIT_FILL;
-        fill_waiting = true;
+      if (!try_launch_b(S, b, &err)) {
+        b->phase = P_WAIT_FILL;
+        for (Req *q : b->reqs) q->phase = P_WAIT_FILL;
+        fill_need = std::max(fill_need, align_up((size_t)b->total * 4, kGrain));
       } else if (err != ABX_OK) {
-        finish(S, q, err);
+        finish_batch(S, b, err);
       }
       continue;
     }
-    if (q->r.kind == ABX_REQ_NEAREST) nearest_offsets(q);
-    finish(S, q, ABX_OK);
+    complete_batch(S, b);
   }
   // 1b. fills that wait on each other: when every occupied slot holds a fill
   // waiting for memory, no running phase will free any, and each may be
-  // blocked by the others' reservations.  The earliest request keeps its
-  // slot; the later ones give their reservations back and return to the
-  // head of the queue (to be counted again once the earliest has finished).
-  if (fill_waiting) {
-    Req *keep = nullptr;
+  // blocked by the others' reservations.  The earliest batch keeps its slot;
+  // the later ones give their reservations back and return to the head of
+  // the queue (to be counted again once the earliest has finished).
+  if (fill_need > 0) {
+    Batch *keep = nullptr;
     bool running = false;
     for (auto &sl : S->slots) {
-      if (!sl.r) continue;
-      if (sl.r->phase != P_WAIT_FILL) {
-        running = true;
-      } else if (!keep || sl.r->ticket < keep->ticket) {
-        keep = sl.r;
-      }
+      if (!sl.b) continue;
+      if (sl.b->phase != P_WAIT_FILL) running = true;
+      else if (!keep || sl.b->reqs.front()->ticket < keep->reqs.front()->ticket) keep = sl.b;
     }
     if (!running && keep) {
-      std::vector<Req *> back;
-      for (auto &sl : S->slots) {
-        Req *q = sl.r;
-        if (!q || q == keep) continue;
-        release_block(S->dev, q->dev_a);
-        release_block(S->dev, q->dev_b);
-        release_block(S->host, q->host);
-        q->phase = P_QUEUED;
-        q->slot = -1;
-        q->total = 0;
-        sl.r = nullptr;
-        S->in_flight--;
-        S->st.requeued++;
-        back.push_back(q);
-      }
-      std::sort(back.begin(), back.end(), [](const Req *a, const Req *b) { return a->ticket > b->ticket; });
-      for (Req *q : back) S->queue.push_front(q);
-      if (!back.empty()) changed = true;
+      for (auto &sl : S->slots)
+        if (sl.b && sl.b != keep) {
+          requeue_batch(S, sl.b);
+          changed = true;
+        }
     }
   }
-  // 2. admission: FIFO, stop while a fill waits for memory (it drains the device)
-  while (!fill_waiting && !S->queue.empty()) {
+  // 2. admission.  The queue is served in order, each size class (small:
+  // at most small_queries queries, large: more) first in first out, but a
+  // request may pass one of the other class that cannot start: a large
+  // request waits when slots - 1 large batches run (a slot stays for small
+  // ones) or when its memory is not there, and small requests behind it go
+  // ahead; the same the other way round.  While a fill waits for device
+  // memory, a batch is admitted only if that memory stays free.
+  int large_running = 0;
+  for (auto &sl : S->slots)
+    if (sl.b && sl.b->large) ++large_running;
+  const int max_large = std::max(1, (int)S->slots.size() - 1);
+  bool blocked[2] = {false, false};  // [large]
+  for (auto it = S->queue.begin(); it != S->queue.end();) {
     int free_slot = -1;
     for (size_t i = 0; i < S->slots.size(); ++i)
-      if (!S->slots[i].r) {
+      if (!S->slots[i].b) {
         free_slot = (int)i;
         break;
       }
     if (free_slot < 0) break;
-    Req *q = S->queue.front();
-    const size_t db = dev_bytes_a(S, q), hb = host_bytes_a(q);
-    if (db > S->dev.size() || hb > S->host.size()) {  // can never fit
-      S->queue.pop_front();
-      S->in_flight++;
-      finish(S, q, ABX_ERR_CAPACITY);
-      changed = true;
+    Req *q = *it;
+    const bool large = is_large(S, q);
+    if (blocked[large] || (large && large_running >= max_large)) {
+      blocked[large] = true;
+      if (blocked[0] && blocked[1]) break;
+      ++it;
       continue;
     }
-    if (!take(S->dev, q->dev_a, db)) break;
-    if (!take(S->host, q->host, hb)) {
-      release_block(S->dev, q->dev_a);
-      break;
+    if (fill_need > 0) {
+      Batch probe;
+      probe.kind = q->r.kind;
+      probe.kk = q->kk;
+      probe.M = q->r.m;
+      if (S->dev.used() + dev_bytes_a(&probe) + fill_need > S->dev.size()) {
+        blocked[large] = true;
+        if (blocked[0] && blocked[1]) break;
+        ++it;
+        continue;
+      }
     }
-    S->queue.pop_front();
-    q->slot = free_slot;
-    q->phase = P_RUN_A;
-    q->t_admit = now_s();
-    S->slots[free_slot].r = q;
-    S->in_flight++;
-    S->st.max_in_flight = std::max<int64_t>(S->st.max_in_flight, S->in_flight);
-    changed = true;
-    const abx_status e = launch_a(S, q);
-    if (e != ABX_OK) finish(S, q, e);
+    // the iterator is invalidated by admission (members leave the queue):
+    // restart from the front, where the earlier blocked requests are skipped
+    // again by their class flags
+    const ptrdiff_t pos = it - S->queue.begin();
+    if (admit(S, it, free_slot)) {
+      changed = true;
+      if (large) ++large_running;
+      // members left the queue: rescan from the front (the requests before
+      // `pos` are of blocked classes and are skipped again)
+      it = S->queue.begin();
+    } else {
+      // admit() put the requests back in ticket order, the failed head at `pos`
+      blocked[large] = true;
+      if (blocked[0] && blocked[1]) break;
+      it = S->queue.begin() + pos + 1;
+    }
   }
   S->st.device_high_water = S->dev.high();
   S->st.host_high_water = S->host.high();
@@ -468,7 +698,7 @@ void abandon_waiting(abx_server *S) {
     finish(S, q, ABX_ERR_INVALID_ARG);
   }
   for (auto &sl : S->slots)
-    if (sl.r && sl.r->phase == P_WAIT_FILL) finish(S, sl.r, ABX_ERR_INVALID_ARG);
+    if (sl.b && sl.b->phase == P_WAIT_FILL) finish_batch(S, sl.b, ABX_ERR_INVALID_ARG);
 }
 
 void scheduler(abx_server *S) {
@@ -517,6 +747,8 @@ abx_status abx_server_create(const abx_server_config *cfg, abx_server **out) {
   abx_server *S = new (std::nothrow) abx_server;
   if (!S) return ABX_ERR_INVALID_ARG;
   S->cfg = *cfg;
+  S->merge_queries = cfg->merge_queries == 0 ? 32768 : std::max<int64_t>(0, cfg->merge_queries);
+  S->small_queries = cfg->small_queries > 0 ? cfg->small_queries : 8192;
   S->dev.reset(cfg->arena_bytes);
   S->host.reset(cfg->host_bytes);
   S->dev_base = static_cast<char *>(cfg->arena);

@@ -99,6 +99,28 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
     // a tree has n-1 internal nodes, each visited at most once: the bound
     // only guarantees termination
     for (int64_t it = 0; it < t.n; ++it) {
+      if constexpr (FMT == ABX_NODES_Q16W) {
+        // 4-wide node: emit the leaf children that pass, descend into the
+        // first internal one, defer the others
+        Kids4 k;
+        load_kids4<KIND>(t, node, k);
+        if (MODE == MODE_STATS) ++visited;
+        int32_t next = -1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (k.ref[j] == kEmptyRef || !q.test(k.b[j])) continue;
+          if (k.ref[j] < 0) leaf(~k.ref[j]);
+          else if (next < 0) next = k.ref[j];
+          else if (sp < kMaxDepth) stack_push<int32_t, kLdsDepthSpatial, kTravBlock>(lds, ovf, sp, nl, k.ref[j]);
+        }
+        if (next >= 0) {
+          node = next;
+        } else {
+          if (sp == 0) break;
+          node = stack_pop<int32_t, kLdsDepthSpatial, kTravBlock>(lds, ovf, sp, nl);
+        }
+        continue;
+      }
       Kids k;
       load_kids<KIND, FMT>(t, node, k);
       if (MODE == MODE_STATS) ++visited;
@@ -131,7 +153,7 @@ __global__ __launch_bounds__(kTravBlock) void k_spatial(TreeArgs t, QueryArgs qa
 // Pass 1 over one tree: one lane per query, queries in Morton order.
 template <int KIND, int FMT, int K, bool STATS>
 __global__ __launch_bounds__(kTravBlock)
-__attribute__((amdgpu_waves_per_eu(nearest_waves_per_eu(K)))) void k_nearest(TreeArgs t, PlainMap map,
+__attribute__((amdgpu_waves_per_eu(nearest_waves_per_eu(K, FMT)))) void k_nearest(TreeArgs t, PlainMap map,
                                                         const float *__restrict__ pts, int64_t m,
                                                         const int32_t *__restrict__ order,
                                                         int32_t *__restrict__ indices,
@@ -243,6 +265,62 @@ __global__ __launch_bounds__(kHeapLanes) __attribute__((amdgpu_waves_per_eu(4)))
     int32_t node = t.root;
     for (int64_t it = 0; it < 2 * t.n; ++it) {
       if (STATS) ++visited;
+      if constexpr (FMT == ABX_NODES_Q16W) {
+        // 4-wide node, as knn_visit_w: leaves offered, the qualifying
+        // internal children visited nearest box centre first
+        Kids4 c;
+        load_kids4<KIND>(t, node, c);
+        float d[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          d[j] = c.ref[j] == kEmptyRef ? INFINITY
+                                       : box_dist2(c.b[j][0], c.b[j][1], c.b[j][2], c.b[j][3],
+                                                   c.b[j][4], c.b[j][5], q.x, q.y, q.z);
+          if (c.ref[j] < 0 && c.ref[j] != kEmptyRef) leaf(~c.ref[j], d[j]);
+        }
+        const float thr = kth();
+        float key[4];
+        int32_t r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool g = c.ref[j] >= 0 && d[j] <= thr;
+          float cc = 0.0f;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float qa = a == 0 ? q.x : (a == 1 ? q.y : q.z);
+            const float mm = (c.b[j][a] - qa) - (qa - c.b[j][3 + a]);
+            cc = __fmaf_rn(mm, mm, cc);
+          }
+          key[j] = g ? cc : INFINITY;
+          r[j] = g ? c.ref[j] : -1;
+        }
+        auto cx = [&](int i, int j) {
+          if (key[j] < key[i] || (r[i] < 0 && r[j] >= 0)) {
+            const float tk = key[i];
+            key[i] = key[j];
+            key[j] = tk;
+            const int32_t tr = r[i];
+            r[i] = r[j];
+            r[j] = tr;
+            const float td = d[i];
+            d[i] = d[j];
+            d[j] = td;
+          }
+        };
+        cx(0, 1);
+        cx(2, 3);
+        cx(0, 2);
+        cx(1, 3);
+        cx(1, 2);
+#pragma unroll
+        for (int j = 3; j >= 1; --j)
+          if (r[j] >= 0 && sp < kMaxDepth)
+            stack_push2<kLdsDepthNearest, kHeapLanes>(lds_n, lds_d, ovf_n, ovf_d, sp, nl, r[j], d[j]);
+        node = r[0];
+        if (node < 0) node = knn_pop<kHeapLanes>(kth(), lds_n, lds_d, ovf_n, ovf_d, sp, nl);
+        if (node < 0) break;
+        continue;
+      }
       Kids c;
       load_kids<KIND, FMT>(t, node, c);
       const float dl = box_dist2(c.l[0], c.l[1], c.l[2], c.l[3], c.l[4], c.l[5], q.x, q.y, q.z);
@@ -347,6 +425,7 @@ TreeArgs tree_args(const abx_bvh *b) {
   t.scene_dev = b->hdr()->scene;
   t.qframe = nullptr;
   t.guard = nullptr;  // the build checked the header before making the handle
+  t.nint = b->nint;
   return t;
 }
 
@@ -386,6 +465,8 @@ abx_status spatial_pred(const abx_bvh *b, const QueryArgs &qa, int mode, int32_t
                         const int32_t *offsets, int32_t *indices, hipStream_t s) {
   if (b->format == ABX_NODES_FP32)
     return spatial_fmt<KIND, PRED, ABX_NODES_FP32>(b, qa, mode, counts, offsets, indices, s);
+  if (b->format == ABX_NODES_Q16W)
+    return spatial_fmt<KIND, PRED, ABX_NODES_Q16W>(b, qa, mode, counts, offsets, indices, s);
   return spatial_fmt<KIND, PRED, ABX_NODES_Q16>(b, qa, mode, counts, offsets, indices, s);
 }
 
@@ -570,26 +651,27 @@ abx_status launch_nearest(const abx_bvh *b, const float *pts, int64_t m, const i
                           int64_t state_cap, int64_t budget, hipStream_t s) {
   if (m == 0 || k == 0) return ABX_OK;
   if (k > kMaxHeapK) return ABX_ERR_UNSUPPORTED;
+#define ABX_BY_FORMAT(CALL, KD)                                      \
+  do {                                                               \
+    if (b->format == ABX_NODES_FP32) return CALL(KD, ABX_NODES_FP32); \
+    if (b->format == ABX_NODES_Q16W) return CALL(KD, ABX_NODES_Q16W); \
+    return CALL(KD, ABX_NODES_Q16);                                  \
+  } while (0)
   if (k > kMaxRegK) {
-    if (b->kind == ABX_PRIM_POINTS) {
-      if (b->format == ABX_NODES_FP32)
-        return nearest_heap<ABX_PRIM_POINTS, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, s);
-      return nearest_heap<ABX_PRIM_POINTS, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, s);
-    }
-    if (b->format == ABX_NODES_FP32)
-      return nearest_heap<ABX_PRIM_BOXES, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, s);
-    return nearest_heap<ABX_PRIM_BOXES, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, s);
+#define ABX_HEAP(KD, FM) nearest_heap<KD, FM>(b, pts, m, order, k, idx, dist, stats, s)
+    if (b->kind == ABX_PRIM_POINTS) ABX_BY_FORMAT(ABX_HEAP, ABX_PRIM_POINTS);
+    ABX_BY_FORMAT(ABX_HEAP, ABX_PRIM_BOXES);
+#undef ABX_HEAP
   }
-  const NearestScratch ns{heavy_q, heavy_bound, counters, effective_budget(budget, m), heavy_state,
+  // a 4-wide walk makes about half as many node visits as a binary one
+  const int64_t b_eff = b->format == ABX_NODES_Q16W ? std::max<int64_t>(1, budget / 2) : budget;
+  const NearestScratch ns{heavy_q, heavy_bound, counters, effective_budget(b_eff, m), heavy_state,
                           (uint32_t)std::min<int64_t>(state_cap, kMaxSavedHeavy)};
-  if (b->kind == ABX_PRIM_POINTS) {
-    if (b->format == ABX_NODES_FP32)
-      return nearest_fmt<ABX_PRIM_POINTS, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, ns, s);
-    return nearest_fmt<ABX_PRIM_POINTS, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, ns, s);
-  }
-  if (b->format == ABX_NODES_FP32)
-    return nearest_fmt<ABX_PRIM_BOXES, ABX_NODES_FP32>(b, pts, m, order, k, idx, dist, stats, ns, s);
-  return nearest_fmt<ABX_PRIM_BOXES, ABX_NODES_Q16>(b, pts, m, order, k, idx, dist, stats, ns, s);
+#define ABX_FMT(KD, FM) nearest_fmt<KD, FM>(b, pts, m, order, k, idx, dist, stats, ns, s)
+  if (b->kind == ABX_PRIM_POINTS) ABX_BY_FORMAT(ABX_FMT, ABX_PRIM_POINTS);
+  ABX_BY_FORMAT(ABX_FMT, ABX_PRIM_BOXES);
+#undef ABX_FMT
+#undef ABX_BY_FORMAT
 }
 
 int max_tree_depth() { return kMaxDepth; }

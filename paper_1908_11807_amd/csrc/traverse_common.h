@@ -19,12 +19,18 @@ constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 65..128
 // Occupancy target of the one-lane nearest pass (waves per SIMD).  Six beat
 // eight at k = 10 on the C3 shell (fewer walks competing for L2, no spills);
 // the k = 32 list alone takes 64 registers.
-constexpr int nearest_waves_per_eu(int K) { return K > 48 ? 2 : (K > 16 ? 3 : (K > 10 ? 4 : (K > 4 ? 6 : 8))); }
+// 4-wide walks hold four slots' distances and keys: at the binary targets
+// they spilled (66 registers at k = 10); these targets leave them unspilled.
+constexpr int nearest_waves_per_eu(int K, int FMT = 0) {
+  return FMT == ABX_NODES_Q16W ? (K > 16 ? 2 : (K > 10 ? 3 : (K > 4 ? 5 : 6)))
+                               : (K > 48 ? 2 : (K > 16 ? 3 : (K > 10 ? 4 : (K > 4 ? 6 : 8))));
+}
 
 struct TreeArgs {
   const void *nodes;
   const void *leaves;
   int64_t n;
+  int64_t nint;            // internal nodes stored (n - 1; fewer for 4-wide nodes)
   int32_t root;            // internal node at the root (n >= 2)
   float scene[6];
   float qo[3], qs[3];
@@ -119,6 +125,35 @@ __device__ __forceinline__ void load_kids(const TreeArgs &t, int32_t node, Kids 
       const int ax = j % 3;
       const float v = deq(q, t.qs[ax], t.qo[ax]);
       k.r[j] = pr ? __uint_as_float(w[3 + ax]) : v;
+    }
+  }
+}
+
+// The four children of a 4-wide node (FMT == ABX_NODES_Q16W).  An unused
+// slot has reference kEmptyRef and is never taken.
+struct Kids4 {
+  float b[4][6];
+  int32_t ref[4];
+};
+
+template <int KIND>
+__device__ __forceinline__ void load_kids4(const TreeArgs &t, int32_t node, Kids4 &k) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(t.nodes) + 4 * (int64_t)node;
+  const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
+  const uint32_t w[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+  k.ref[0] = (int32_t)d.x;
+  k.ref[1] = (int32_t)d.y;
+  k.ref[2] = (int32_t)d.z;
+  k.ref[3] = (int32_t)d.w;
+#pragma unroll
+  for (int c4 = 0; c4 < 4; ++c4) {
+    const bool pt = KIND == ABX_PRIM_POINTS && k.ref[c4] < 0;  // a point leaf (or unused)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint32_t q = (w[3 * c4 + j / 2] >> (16 * (j & 1))) & 0xffffu;
+      const int ax = j % 3;
+      const float v = deq(q, t.qs[ax], t.qo[ax]);
+      k.b[c4][j] = pt ? __uint_as_float(w[3 * c4 + ax]) : v;
     }
   }
 }
@@ -320,11 +355,11 @@ __device__ __forceinline__ void knn_leaf(const TreeArgs &t, const KnnQuery &q, i
 // or -1 when neither qualifies.  `bound` is an external upper bound of the
 // final k-th distance (+inf when there is none).
 template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest, bool DEFER = false>
-__device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &q, int32_t node,
-                                             float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
-                                             ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
-                                             int &sp, int &nl, int32_t &reads,
-                                             KnnPending *pend = nullptr) {
+__device__ __forceinline__ int32_t knn_visit2(const TreeArgs &t, const KnnQuery &q, int32_t node,
+                                              float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
+                                              ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
+                                              int &sp, int &nl, int32_t &reads,
+                                              KnnPending *pend = nullptr) {
   Kids c;
   load_kids<KIND, FMT>(t, node, c);
   const float dl = box_dist2(c.l[0], c.l[1], c.l[2], c.l[3], c.l[4], c.l[5], q.x, q.y, q.z);
@@ -371,6 +406,120 @@ __device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &
   if (gl) return c.lref;
   if (gr) return c.rref;
   return -1;
+}
+
+// One 4-wide node decoded for a walk: per slot the squared box distance to
+// q (+inf for an unused slot), the squared distance to the box centre
+// (times 4; visit order only) and the reference.
+template <int KIND>
+__device__ __forceinline__ void wide_slots(const TreeArgs &t, int32_t node, const KnnQuery &q,
+                                           float d[4], float key[4], int32_t r[4]) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(t.nodes) + 4 * (int64_t)node;
+  const uint4 a = p[0], b = p[1], c = p[2], e = p[3];
+  const uint32_t w[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+  r[0] = (int32_t)e.x;
+  r[1] = (int32_t)e.y;
+  r[2] = (int32_t)e.z;
+  r[3] = (int32_t)e.w;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const bool pt = KIND == ABX_PRIM_POINTS && r[j] < 0;  // a point leaf (or unused)
+    float lo[3], hi[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const uint32_t ql = (w[3 * j + ax / 2] >> (16 * (ax & 1))) & 0xffffu;
+      const uint32_t qh = (w[3 * j + (ax + 3) / 2] >> (16 * ((ax + 3) & 1))) & 0xffffu;
+      const float pv = __uint_as_float(w[3 * j + ax]);
+      lo[ax] = pt ? pv : deq(ql, t.qs[ax], t.qo[ax]);
+      hi[ax] = pt ? pv : deq(qh, t.qs[ax], t.qo[ax]);
+    }
+    d[j] = r[j] == kEmptyRef ? INFINITY
+                             : box_dist2(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], q.x, q.y, q.z);
+    const float qv[3] = {q.x, q.y, q.z};
+    float cc = 0.0f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float m = (lo[ax] - qv[ax]) - (qv[ax] - hi[ax]);
+      cc = __fmaf_rn(m, m, cc);
+    }
+    key[j] = cc;
+  }
+}
+
+// The same step over a 4-wide node: leaf children are offered as above;
+// the qualifying internal children are visited nearest box centre first:
+// the nearest is returned and the others are pushed farthest first, so they
+// come off the stack in the same order.
+template <int KIND, int K, int B, int S = kLdsDepthNearest, bool DEFER = false>
+__device__ __forceinline__ int32_t knn_visit_w(const TreeArgs &t, const KnnQuery &q, int32_t node,
+                                               float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
+                                               ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
+                                               int &sp, int &nl, int32_t &reads,
+                                               KnnPending *pend = nullptr) {
+  // each slot is decoded straight into its box distance and centre key, so
+  // the 24 coordinates are never live together (they made the walk spill)
+  float d[4], key[4];
+  int32_t r[4];
+  wide_slots<KIND>(t, node, q, d, key, r);
+  if (DEFER && exact_leaf_slots<KIND, ABX_NODES_Q16W>()) {
+    const float thr0 = fminf(L.kth(), bound);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (r[j] < 0 && r[j] != kEmptyRef && d[j] <= thr0) pend->park(L, knn_key(d[j], ~r[j]));
+    pend->flush_some(L);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (r[j] < 0 && r[j] != kEmptyRef)
+        knn_leaf<KIND, ABX_NODES_Q16W, K>(t, q, ~r[j], d[j], fminf(L.kth(), bound), L, reads);
+  }
+  const float thr = fminf(L.kth(), bound);
+  // the qualifying internal children keep their key; the others sort last
+  // with reference -1
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const bool g = r[j] >= 0 && d[j] <= thr;
+    key[j] = g ? key[j] : INFINITY;
+    r[j] = g ? r[j] : -1;
+  }
+  // sorting network on four (key, reference, distance) triples; a NaN key
+  // only changes the order, never drops a child
+  auto cx = [&](int i, int j) {
+    if (key[j] < key[i] || (r[i] < 0 && r[j] >= 0)) {
+      const float tk = key[i];
+      key[i] = key[j];
+      key[j] = tk;
+      const int32_t tr = r[i];
+      r[i] = r[j];
+      r[j] = tr;
+      const float td = d[i];
+      d[i] = d[j];
+      d[j] = td;
+    }
+  };
+  cx(0, 1);
+  cx(2, 3);
+  cx(0, 2);
+  cx(1, 3);
+  cx(1, 2);
+#pragma unroll
+  for (int j = 3; j >= 1; --j)
+    if (r[j] >= 0 && sp < kMaxDepth) stack_push2<S, B>(lds_n, lds_d, ovf_n, ovf_d, sp, nl, r[j], d[j]);
+  return r[0];
+}
+
+template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest, bool DEFER = false>
+__device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &q, int32_t node,
+                                             float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
+                                             ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
+                                             int &sp, int &nl, int32_t &reads,
+                                             KnnPending *pend = nullptr) {
+  if constexpr (FMT == ABX_NODES_Q16W)
+    return knn_visit_w<KIND, K, B, S, DEFER>(t, q, node, bound, L, lds_n, lds_d, ovf_n, ovf_d, sp,
+                                             nl, reads, pend);
+  else
+    return knn_visit2<KIND, FMT, K, B, S, DEFER>(t, q, node, bound, L, lds_n, lds_d, ovf_n, ovf_d,
+                                                 sp, nl, reads, pend);
 }
 
 // pop deferred nodes until one still qualifies; -1 when the stack runs dry
@@ -542,11 +691,12 @@ constexpr int kCoopShareLog2 = 3;
 // so the k best of all lists, taken in (distance, index) order, are the
 // exact answer: each wavefront merges its 64 lists, then the first merges
 // the W results.  Runs as a persistent grid draining the heavy list.
-template <int W>
+template <int W, int A = 2>
 struct CoopShape {
   static constexpr int kThreads = W * kWave;
-  static constexpr int kFront = 256 * W;     // frontier size at which the threads split up
-  static constexpr int kCap = 2 * kFront;    // >= 2 * (kFront - 1): one expansion's output
+  static constexpr int kCap = 512 * W;       // entries of a frontier buffer
+  static constexpr int kFront = kCap / A;    // frontier size at which the threads split up:
+                                             // one expansion of A-ary nodes stays below kCap
   static constexpr int kWindow = kCap / kThreads;  // LDS stack entries per thread
 };
 
@@ -559,7 +709,7 @@ template <int KIND, int FMT, int K, class Map, int W>
 __global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
     TreeArgs t, Map map, const float *__restrict__ pts, int32_t *__restrict__ indices,
     float *__restrict__ dist, HeavyList heavy) {
-  using S = CoopShape<W>;
+  using S = CoopShape<W, FMT == ABX_NODES_Q16W ? 4 : 2>;
   static_assert(kHeavyStateEntries < S::kFront, "a saved walk fits the first frontier");
   // two frontier buffers; during the depth-first phase the one not holding
   // the final frontier is the threads' stack window
@@ -597,7 +747,7 @@ __global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
       bool bad = false;
       for (int e = tid; e < c; e += S::kThreads) {
         const int32_t nd = st[2 + 2 * e];
-        bad |= nd < 0 || nd >= t.n - 1;
+        bad |= nd < 0 || nd >= t.nint;
       }
       if (__syncthreads_or(bad)) c = -1;
     }
@@ -629,6 +779,49 @@ __global__ __launch_bounds__(CoopShape<W>::kThreads) void k_nearest_coop(
       const float bnd = __uint_as_float(s_bound);
       for (int base = 0; base < fsize; base += S::kThreads) {
         const int e = base + tid;
+        if constexpr (FMT == ABX_NODES_Q16W) {
+          bool ek[4] = {false, false, false, false};
+          int32_t rk[4] = {0, 0, 0, 0};
+          float dk[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (e < fsize && s_fd[cur][e] <= fminf(L.kth(), bnd)) {
+            Kids4 c;
+            load_kids4<KIND>(t, s_fn[cur][e], c);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              dk[j] = c.ref[j] == kEmptyRef ? INFINITY
+                                            : box_dist2(c.b[j][0], c.b[j][1], c.b[j][2], c.b[j][3],
+                                                        c.b[j][4], c.b[j][5], q.x, q.y, q.z);
+              if (c.ref[j] < 0 && c.ref[j] != kEmptyRef)
+                knn_leaf<KIND, FMT, K>(t, q, ~c.ref[j], dk[j], fminf(L.kth(), bnd), L, reads);
+            }
+            const float thr = fminf(L.kth(), bnd);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              ek[j] = c.ref[j] >= 0 && dk[j] <= thr;
+              rk[j] = c.ref[j];
+            }
+          }
+          uint64_t bk[4];
+          int cnt = 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            bk[j] = __ballot(ek[j]);
+            cnt += __popcll(bk[j]);
+          }
+          uint32_t o = 0;
+          if (lane == 0 && cnt > 0) o = atomicAdd(&s_size[cur ^ 1], (uint32_t)cnt);
+          int at0 = (int)__shfl(o, 0, kWave);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (ek[j]) {
+              const int at = at0 + __popcll(bk[j] & lt);
+              s_fn[cur ^ 1][at] = rk[j];
+              s_fd[cur ^ 1][at] = dk[j];
+            }
+            at0 += __popcll(bk[j]);
+          }
+          continue;
+        }
         bool el = false, er = false;
         int32_t lref = 0, rref = 0;
         float dl = 0.0f, dr = 0.0f;

@@ -218,3 +218,92 @@ def dequantise(qbox, origin, scale):
         a = c % 3
         out[..., c] = fmaf32(qbox[..., c], scale[a], origin[a])
     return out
+
+
+# ---------------------------------------------------------------- 4-wide trees
+EMPTY_REF = -2 ** 31
+
+
+def expected_wide(ref, prims, kind, n):
+    """The oracle's binary hierarchy collapsed at even depths: each internal
+    node at even depth keeps its children's children (a leaf child stays a
+    leaf child), numbered in depth-first order (left subtree first).
+    Returns (refs int64 [W, 4]: node index, ~primitive for a leaf, EMPTY_REF
+    for an unused slot; exact child boxes float32 [W, 4, 6], NaN when unused)."""
+    ni = n - 1
+    ck, ci, perm = ref["child_kind"], ref["child_index"], ref["perm"]
+    sp = np.asarray(prims, np.float32).reshape(n, -1)[perm]
+    leafbox = np.concatenate([sp[:, :3], sp[:, :3]], axis=1) if kind == 0 else sp
+    depth = np.zeros(ni, np.int64)
+    order = []
+    stack = [0]
+    while stack:
+        u = stack.pop()
+        order.append(u)
+        for s in (1, 0):   # left child popped first
+            if ck[u, s] == 1:
+                depth[ci[u, s]] = depth[u] + 1
+                stack.append(ci[u, s])
+    even = [u for u in order if depth[u] % 2 == 0]
+    widx = np.full(ni, -1, np.int64)
+    widx[np.array(even, np.int64)] = np.arange(len(even))
+    refs = np.full((len(even), 4), EMPTY_REF, np.int64)
+    cbox = np.full((len(even), 4, 6), np.nan, np.float32)
+    for w, u in enumerate(even):
+        slots = []
+        for s in (0, 1):
+            if ck[u, s] == 0:
+                slots.append((0, ci[u, s]))
+            else:
+                c = ci[u, s]
+                slots.extend((int(ck[c, s2]), ci[c, s2]) for s2 in (0, 1))
+        for j, (internal, x) in enumerate(slots):
+            if internal:
+                refs[w, j] = widx[x]
+                cbox[w, j] = ref["boxes"][x]
+            else:
+                refs[w, j] = ~perm[x]
+                cbox[w, j] = leafbox[x]
+    return refs, cbox
+
+
+def check_wide_tree(orc, prims, kind, bits, bvh):
+    """A 4-wide tree against the oracle's hierarchy collapsed at even depths:
+    the same node count, the same references slot by slot, point leaves'
+    exact coordinates, every quantised slot containing its exact box, and the
+    leaf region (permutation, or the exact box records of a box tree)."""
+    n = bvh.n
+    ref = orc.build(prims, kind, bits)
+    lay = bvh.layout
+    leaves = bvh.leaves_bytes().cpu().numpy()
+    if kind == 0:
+        assert np.array_equal(leaves.view(np.int32).astype(np.int64), ref["perm"])
+    else:
+        rec = leaves.view(np.float32).reshape(n, 8)
+        np.testing.assert_array_equal(rec[:, :6], np.asarray(prims, np.float32).reshape(n, 6))
+        pos = leaves.view(np.int32).reshape(n, 8)[:, 6].astype(np.int64)
+        assert np.array_equal(ref["perm"][pos], np.arange(n))
+    if n < 2:
+        assert int(lay.node_count) == 0
+        return
+    want_refs, want_box = expected_wide(ref, prims, kind, n)
+    W = want_refs.shape[0]
+    assert int(lay.node_count) == W
+    raw = bvh.nodes_bytes().cpu().numpy()
+    assert raw.size == 64 * W
+    refs = raw.view(np.int32).reshape(W, 16)[:, 12:16].astype(np.int64)
+    assert np.array_equal(refs, want_refs)
+    u16 = raw.view(np.uint16).reshape(W, 32)
+    f32 = raw.view(np.float32).reshape(W, 16)
+    for j in range(4):
+        used = refs[:, j] != EMPTY_REF
+        pleaf = used & (refs[:, j] < 0) & (kind == 0)
+        np.testing.assert_array_equal(f32[pleaf, 3 * j:3 * j + 3], want_box[pleaf, j, :3])
+        qs = used & ~pleaf
+        d = dequantise(u16[qs, 6 * j:6 * j + 6].astype(np.uint32), list(lay.q16_origin),
+                       list(lay.q16_scale))
+        bad = ~(np.all(d[:, :3] <= want_box[qs, j, :3], axis=1) & np.all(d[:, 3:] >= want_box[qs, j, 3:], axis=1))
+        assert not bad.any(), (f"slot {j}: quantised box not outward at nodes {np.nonzero(qs)[0][bad][:4]}: "
+                               f"codes {u16[qs, 6 * j:6 * j + 6][bad][:2]}, dequantised {d[bad][:2]}, "
+                               f"exact {want_box[qs, j][bad][:2]}, origin {list(lay.q16_origin)}, "
+                               f"scale {list(lay.q16_scale)}")

@@ -57,6 +57,7 @@ def test_serving_results_alone_equal_mix(orc):
     st = s4.stats()
     s4.close()
     assert st["completed"] == len(reqs) and st["device_high_water"] <= 2 << 20
+    assert st["batches"] < len(reqs)                   # some requests were merged
     for r, a, b in zip(reqs, alone, mix):
         assert a["status"] == abx.OK and b["status"] == abx.OK
         assert np.array_equal(a["offsets"], b["offsets"])
@@ -114,3 +115,36 @@ def test_serving_large_k_equals_direct_query(orc):
     assert np.array_equal(r["distances"].reshape(777, 100), dd.cpu().numpy())
     check_nearest(orc, pts, 0, q, 100, r["indices"].reshape(777, 100),
                   r["distances"].reshape(777, 100), rows=np.arange(0, 777, 31))
+
+
+def test_serving_merged_tiny_requests_equal_direct_queries(orc):
+    # many tiny requests of one class queued behind a long one: they run as
+    # merged launches, each request's rows equal the direct call's
+    pts = datagen.shell(200_000, 21, 0.99, 1.01)
+    tree = abx.bvh_build(torch.from_numpy(pts).cuda(), node_format="q16")
+    s = abx.Server(slots=1, budget_bytes=512 << 20, host_bytes=512 << 20)
+    tid = s.add_tree(tree)
+    long_q = datagen.uniform_cube(100_000, 22, -1.0, 1.0)
+    first = s.submit(tid, abx.REQ_NEAREST, long_q, k=32)
+    qs = [datagen.uniform_cube(int(m), 30 + i, -1.0, 1.0) for i, m in enumerate(
+        np.random.default_rng(23).integers(1, 400, size=60))]
+    tk = [s.submit(tid, abx.REQ_NEAREST, q, k=8) for q in qs]
+    tr = [s.submit(tid, abx.REQ_RADIUS, q, radius=0.01) for q in qs[:20]]
+    res = [s.wait(t) for t in tk]
+    rres = [s.wait(t) for t in tr]
+    assert s.wait(first)["status"] == abx.OK
+    st = s.stats()
+    s.close()
+    assert st["batches"] < len(tk) + len(tr)
+    for q, r in zip(qs, res):
+        assert r["status"] == abx.OK
+        _, di, dd = abx.query_nearest(tree, torch.from_numpy(q).cuda(), 8)
+        assert np.array_equal(r["indices"], di.cpu().numpy().reshape(-1))
+        assert np.array_equal(r["distances"], dd.cpu().numpy().reshape(-1))
+    for q, r in zip(qs[:20], rres):
+        assert r["status"] == abx.OK
+        do, dx = abx.query_spatial(tree, torch.from_numpy(q).cuda(), radius=0.01)
+        assert np.array_equal(r["offsets"], do.cpu().numpy())
+        assert _rows(r) == _rows(dict(offsets=do.cpu().numpy(), indices=dx.cpu().numpy()))
+    check_nearest(orc, pts, 0, qs[0], 8, res[0]["indices"].reshape(-1, 8),
+                  res[0]["distances"].reshape(-1, 8))

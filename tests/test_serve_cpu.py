@@ -8,6 +8,8 @@ from paper_1908_11807_amd import abx
 
 
 def _server(**kw):
+    # one request per launch unless a test asks for merging
+    kw.setdefault("merge_queries", -1)
     s = abx.Server(simulate=True, **kw)
     s.add_tree(None)
     return s
@@ -123,4 +125,100 @@ def test_fills_waiting_on_each_other_are_serialised():
         assert res[t]["status"] == abx.OK and res[t]["total"] == 10 * 1000
     st = s.stats()
     assert st["requeued"] >= 1 and st["device_high_water"] <= budget
+    s.close()
+
+
+def _batches(res):
+    """Requests grouped by launch: the members of one batch share their
+    admission time."""
+    groups = {}
+    for i, r in enumerate(res):
+        groups.setdefault(r["t_admit"], []).append(i)
+    return list(groups.values())
+
+
+def test_small_requests_of_one_class_are_merged():
+    # one slot busy with a long request; the small ones queued behind it
+    # leave together as merged batches
+    s = _server(slots=1, budget_bytes=1 << 30, host_bytes=1 << 28, sim_ns_per_query=2000,
+                merge_queries=2000)
+    q = np.zeros((500, 3), np.float32)
+    first = s.submit(0, abx.REQ_NEAREST, np.zeros((5000, 3), np.float32), k=8)
+    tickets = [s.submit(0, abx.REQ_NEAREST, q, k=8) for _ in range(12)]
+    res = [s.wait(t) for t in tickets]
+    assert s.wait(first)["status"] == abx.OK
+    assert all(r["status"] == abx.OK for r in res)
+    for r in res:
+        assert r["offsets"].tolist() == list(range(0, 8 * 501, 8))
+        # the batch's phase lasts for all its queries
+        assert r["t_device"] >= 500 * 2000e-9 * 0.99
+    groups = _batches(res)
+    assert all(len(g) <= 4 for g in groups)               # 4 x 500 = the 2000-query limit
+    assert len(groups) <= 4 and s.stats()["batches"] <= 5
+    # batches keep the queue's order
+    assert [g[0] for g in groups] == sorted(g[0] for g in groups)
+    s.close()
+
+
+def test_merging_keeps_classes_apart():
+    s = _server(slots=1, budget_bytes=1 << 30, host_bytes=1 << 28, sim_ns_per_query=1000,
+                merge_queries=1 << 20)
+    s.add_tree(None)
+    q = np.zeros((100, 3), np.float32)
+    blocker = s.submit(0, abx.REQ_NEAREST, np.zeros((20_000, 3), np.float32), k=1)
+    kinds = [(0, abx.REQ_NEAREST, 8, 0.0), (0, abx.REQ_NEAREST, 1, 0.0), (0, abx.REQ_RADIUS, 0, 0.1),
+             (1, abx.REQ_NEAREST, 8, 0.0), (0, abx.REQ_RADIUS, 0, 0.2)]
+    subs = [kinds[i % len(kinds)] for i in range(25)]
+    tickets = [s.submit(tr, kd, q, k=k, radius=r) for tr, kd, k, r in subs]
+    res = [s.wait(t) for t in tickets]
+    s.wait(blocker)
+    assert all(r["status"] == abx.OK for r in res)
+    for g in _batches(res):
+        assert len({subs[i] for i in g}) == 1                 # one class per launch
+    assert len(_batches(res)) == len(kinds)                   # each class merged once
+    for i, r in enumerate(res):
+        if subs[i][1] == abx.REQ_RADIUS:
+            assert r["total"] == 10 * 100
+    s.close()
+
+
+def test_small_requests_pass_a_blocked_large_one():
+    # two slots: at most one large batch runs, so a second large request
+    # waits and the small one behind it starts first
+    s = _server(slots=2, budget_bytes=1 << 30, host_bytes=1 << 28, sim_ns_per_query=200,
+                merge_queries=0, small_queries=1000)
+    big = np.zeros((20_000, 3), np.float32)
+    small = np.zeros((10, 3), np.float32)
+    t1 = s.submit(0, abx.REQ_NEAREST, big, k=4)
+    t2 = s.submit(0, abx.REQ_NEAREST, big, k=4)
+    t3 = s.submit(0, abx.REQ_NEAREST, small, k=4)
+    r1, r2, r3 = s.wait(t1), s.wait(t2), s.wait(t3)
+    assert r1["status"] == r2["status"] == r3["status"] == abx.OK
+    assert r3["t_admit"] < r2["t_admit"]                 # passed the waiting large one
+    assert r3["t_done"] < r1["t_done"]
+    assert r2["t_admit"] >= r1["t_done"] - 1e-3          # one large batch at a time
+    s.close()
+
+
+def test_merged_radius_batches_with_host_backpressure():
+    # merged radius batches still reserve each request's result space; the
+    # caller releases results as they complete (with merging, a request can
+    # complete before one submitted earlier, so an arena too small for the
+    # results in flight needs releases in completion order)
+    s = _server(slots=2, budget_bytes=1 << 30, host_bytes=96 * 1024, sim_ns_per_query=100,
+                merge_queries=1000)
+    q = np.zeros((200, 3), np.float32)
+    tickets = [s.submit(0, abx.REQ_RADIUS, q, radius=0.1) for _ in range(20)]
+    live, deadline = set(tickets), abx.server_now() + 20.0
+    while live and abx.server_now() < deadline:
+        for t in list(live):
+            r = s.poll(t)
+            if r is not None:
+                assert r["status"] == abx.OK and r["total"] == 10 * 200
+                s.release(t)
+                live.discard(t)
+    assert not live, s.stats()
+    st = s.stats()
+    assert st["host_high_water"] <= 96 * 1024 and st["completed"] == 20
+    assert st["batches"] < 20
     s.close()

@@ -82,3 +82,42 @@ def test_karras_numbering_roundtrip(case):
     back_rows, back_refs = _karras_numbering(d_rows, d_refs2, n, inv)
     assert np.array_equal(back_rows, rows)
     assert np.array_equal(back_refs, refs)
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_collapsed_wide_tree_structure(case):
+    """The expected 4-wide tree (the binary tree collapsed at even depths)
+    the GPU tree is compared with: every primitive appears once as a leaf
+    child, every node but the root is referenced once, nodes hold 2 to 4
+    children, the count is within the bound the build allocates for, and a
+    node's slots cover exactly the leaves of its binary node."""
+    from parity import EMPTY_REF, expected_wide
+    n, r = list(_trees())[case]
+    p = None
+    for nn, gen in ((2, datagen.uniform_cube), (3, datagen.uniform_cube), (17, datagen.uniform_cube),
+                    (4097, datagen.clusters), (60_000, lambda n, s: datagen.shell(n, s, 0.99, 1.01))):
+        if nn == n:
+            p = gen(n, 5)
+    refs, box = expected_wide(r, p, 0, n)
+    W = refs.shape[0]
+    ni = n - 1
+    assert 1 <= W <= (2 * ni + 1) // 3 + 1
+    used = refs != EMPTY_REF
+    assert np.all(used.sum(axis=1) >= 2)
+    # unused slots come last
+    assert np.all(np.diff(used.astype(np.int8), axis=1) <= 0)
+    leaves = np.sort(~refs[used & (refs < 0)])
+    assert np.array_equal(leaves, np.arange(n))
+    nodes = np.sort(refs[used & (refs >= 0)])
+    assert np.array_equal(nodes, np.arange(1, W))
+    # depth-first numbering: each node's first internal child follows it,
+    # and every child comes after its parent
+    for w in range(W):
+        kids = refs[w][used[w] & (refs[w] >= 0)]
+        assert np.all(kids > w)
+        if kids.size:
+            assert kids[0] == w + 1
+    # the boxes of the root's slots cover the scene box exactly
+    lo = np.nanmin(box[0][used[0], :3], axis=0)
+    hi = np.nanmax(box[0][used[0], 3:], axis=0)
+    np.testing.assert_array_equal(np.concatenate([lo, hi]), r["scene"])
