@@ -537,6 +537,13 @@ double abx_server_now(void);
  *   of the kernels called `name` since the last reset (the host waits on
  *   the events).  The switch and the totals are process-wide and may be
  *   used from any thread; for measurement only. */
+/* abx_inject_fault: a test hook for failure handling.  The (skip + 1)-th
+ *   next event of `kind` fails as a HIP failure would, once: LAUNCH, a
+ *   kernel launch (nothing is launched; the call returns ABX_ERR_HIP) or a
+ *   phase of the server's simulated executor; HOST_ALLOC, the pinned host
+ *   arena of abx_server_create.  skip < 0 disarms.  Process-wide. */
+typedef enum { ABX_FAULT_LAUNCH = 0, ABX_FAULT_HOST_ALLOC = 1 } abx_fault_kind;
+abx_status abx_inject_fault(int32_t kind, int64_t skip);
 const char *abx_status_string(abx_status s);
 int abx_last_hip_error(void);
 const char *abx_version(void);

@@ -25,7 +25,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libabx.so")
+# ABX_LIBRARY: another build of the same library (the thread-sanitised
+# build the tests make of the host code)
+LIB_PATH = os.environ.get("ABX_LIBRARY") or os.path.join(_HERE, "libabx.so")
 
 # status codes (include/abx.h)
 (OK, ERR_INVALID_ARG, ERR_INVALID_INPUT, ERR_CAPACITY, ERR_OVERFLOW, ERR_HIP, ERR_UNSUPPORTED, PENDING,
@@ -150,6 +152,7 @@ def _lib():
             "abx_radix_sort_sizes": [i64, i32, P(sz)],
             "abx_radix_sort_pairs": [vp, vp, i64, i32, vp, vp, vp, sz, vp],
             "abx_radix_sort_check": [vp, i64, i32, vp],
+            "abx_inject_fault": [i32, i64],
             "abx_timing_get": [C.c_char_p, P(C.c_double), P(i64)],
             "abx_forest_build_sizes": [P(ForestPrimitives), P(sz), P(sz)],
             "abx_forest_build": [P(ForestPrimitives), vp, sz, vp, sz, vp, P(vp)],
@@ -482,6 +485,17 @@ def radix_sort_pairs(keys, key_bits, vals=None, check=True):
         _check(L.abx_radix_sort_check(_ptr(scratch), n, int(key_bits), _stream()),
                "abx_radix_sort_check")
     return kout, vout
+
+
+FAULT_LAUNCH, FAULT_HOST_ALLOC = 0, 1
+
+
+def inject_fault(kind, skip=0):
+    """Test hook: the (skip + 1)-th next event of ``kind`` fails once as a HIP
+    failure would (FAULT_LAUNCH: a kernel launch or a simulated server
+    phase; FAULT_HOST_ALLOC: a server's pinned host arena); skip < 0
+    disarms."""
+    _check(_lib().abx_inject_fault(int(kind), int(skip)), "abx_inject_fault")
 
 
 def set_sort_spin_limit(polls):

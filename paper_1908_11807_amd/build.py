@@ -40,9 +40,14 @@ def common_flags() -> list[str]:
     ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *common_flags(), "-c", src, "-o", obj]
+# ThreadSanitizer instruments the host code only (the scheduler and the ABI);
+# device code is built as usual
+TSAN_FLAGS = ["-Xarch_host", "-fsanitize=thread", "-g"]
+
+
+def _compile(src: str, out_dir: str = BUILD_DIR, extra=()) -> str:
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [hipcc(), *common_flags(), *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -68,6 +73,32 @@ def build_library(verbose: bool = True) -> str:
     if verbose:
         print(f"built {LIB}")
     return LIB
+
+
+def tsan_runtime() -> str:
+    """The ThreadSanitizer runtime of the ROCm clang (preloaded into the
+    process that loads the sanitised library)."""
+    import glob as _g
+    for c in sorted(_g.glob("/opt/rocm*/lib/llvm/lib/clang/*/lib/linux/libclang_rt.tsan-x86_64.so")):
+        return c
+    raise RuntimeError("no ThreadSanitizer runtime found under /opt/rocm")
+
+
+def build_tsan_library() -> str:
+    """libabx with its host code built under ThreadSanitizer, in _build/tsan
+    (for the CPU tests of the serving scheduler; never shipped)."""
+    out_dir = os.path.join(BUILD_DIR, "tsan")
+    os.makedirs(out_dir, exist_ok=True)
+    srcs = sources()
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(lambda src: _compile(src, out_dir, TSAN_FLAGS), srcs))
+    lib = os.path.join(out_dir, "libabx_tsan.so")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=thread",
+           "-o", lib, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    return lib
 
 
 if __name__ == "__main__":

@@ -333,6 +333,21 @@ bool stream_capturing(hipStream_t s) {
 
 thread_local int g_no_events = 0;
 
+namespace {
+// per fault kind: -1 off, else the number of events still to let pass
+std::atomic<int64_t> g_fault[2] = {{-1}, {-1}};
+}  // namespace
+
+bool fault_hit(int kind) {
+  if (kind < 0 || kind > 1) return false;
+  std::atomic<int64_t> &c = g_fault[kind];
+  int64_t v = c.load(std::memory_order_relaxed);
+  while (v >= 0) {
+    if (c.compare_exchange_weak(v, v - 1, std::memory_order_relaxed)) return v == 0;
+  }
+  return false;
+}
+
 // no events inside a graph capture: timing is for eager launches only
 bool timing_on(hipStream_t s) {
   return g_timing.load(std::memory_order_relaxed) && g_no_events == 0 && !stream_capturing(s);
@@ -367,6 +382,12 @@ const char *abx_status_string(abx_status s) {
 }
 
 int abx_last_hip_error(void) { return g_last_hip; }
+
+abx_status abx_inject_fault(int32_t kind, int64_t skip) {
+  if (kind != ABX_FAULT_LAUNCH && kind != ABX_FAULT_HOST_ALLOC) return ABX_ERR_INVALID_ARG;
+  g_fault[kind].store(skip < 0 ? -1 : skip, std::memory_order_relaxed);
+  return ABX_OK;
+}
 
 int64_t abx_set_nearest_budget(int64_t visits) {
   return g_nearest_budget.exchange(visits > 0 ? visits : INT64_MAX);

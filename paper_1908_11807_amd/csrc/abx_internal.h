@@ -136,6 +136,10 @@ bool stream_capturing(hipStream_t s);
 bool timing_on(hipStream_t s);      // event timing enabled, `s` not capturing, events allowed
 void timing_record(const char *name, hipEvent_t a, hipEvent_t b);
 
+// Injected faults (abx_inject_fault): true when this event of the kind is
+// the one armed to fail
+bool fault_hit(int kind);
+
 // While one exists on a thread, launches from that thread create no events
 // (entry points that promise to allocate nothing).
 extern thread_local int g_no_events;
@@ -168,6 +172,13 @@ abx_status launch(const char *name, hipStream_t s, F &&f) {
     ABX_HIP(hipEventCreate(&a));
     ABX_HIP(hipEventCreate(&b));
     ABX_HIP(hipEventRecord(a, s));
+  }
+  if (fault_hit(ABX_FAULT_LAUNCH)) {  // a test's injected failure: nothing is launched
+    if (timed) {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+    return hip_fail(hipErrorLaunchFailure);
   }
   f();
   hipError_t e = hipGetLastError();

@@ -254,8 +254,11 @@ void finish(abx_server *S, Req *q, abx_status status) {
 }
 
 // ends a batch: every member finishes with `status` (OK: its results are
-// in place), the batch's memory and slot are released
+// in place), the batch's memory and slot are released.  After a failure
+// part of the batch's work may still be enqueued: the slot's stream is
+// drained first, so no copy or kernel touches memory handed to another batch.
 void finish_batch(abx_server *S, Batch *b, abx_status status) {
+  if (status != ABX_OK && !S->cfg.simulate && b->slot >= 0) (void)hipStreamSynchronize(S->slots[b->slot].s);
   for (Req *q : b->reqs) finish(S, q, status);
   release_block(S->dev, b->dev_a);
   release_block(S->dev, b->dev_b);
@@ -289,6 +292,8 @@ abx_status launch_a(abx_server *S, Batch *b) {
     }
   }
   if (S->cfg.simulate) {
+    // the simulated executor's stand-in for a failed launch
+    if (fault_hit(ABX_FAULT_LAUNCH)) return hip_fail(hipErrorLaunchFailure);
     b->sim_deadline = now_s() + 1e-9 * S->cfg.sim_ns_per_query * (double)(M > 0 ? M : 1);
     return ABX_OK;
   }
@@ -752,6 +757,10 @@ abx_status abx_server_create(const abx_server_config *cfg, abx_server **out) {
   S->dev.reset(cfg->arena_bytes);
   S->host.reset(cfg->host_bytes);
   S->dev_base = static_cast<char *>(cfg->arena);
+  if (fault_hit(ABX_FAULT_HOST_ALLOC)) {  // a test's injected allocation failure
+    delete S;
+    return hip_fail(hipErrorOutOfMemory);
+  }
   if (!cfg->simulate) {
     if (hipGetDevice(&S->device) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&S->host_base), cfg->host_bytes, hipHostMallocDefault) != hipSuccess) {
@@ -776,6 +785,10 @@ abx_status abx_server_create(const abx_server_config *cfg, abx_server **out) {
     }
   } else {
     S->host_base = static_cast<char *>(::operator new(cfg->host_bytes, std::nothrow));
+    if (!S->host_base) {
+      delete S;
+      return ABX_ERR_HIP;
+    }
     S->slots.resize(cfg->slots);
   }
   S->th = std::thread(scheduler, S);

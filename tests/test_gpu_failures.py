@@ -113,3 +113,48 @@ def test_forest_check_reports_device_error(forced_giveup):
     offsets, idx, dist = plan.results()
     torch.cuda.synchronize()
     assert int(offsets[-1]) == 8 * 100 * 3 + 1 * 100
+
+
+def test_injected_launch_failure_is_reported_and_recovered():
+    pts = datagen.uniform_cube(20_000, 50)
+    q = dev(datagen.uniform_cube(5000, 51))
+    t = abx.bvh_build(dev(pts), node_format="q16")
+    want = abx.query_nearest(t, q, 8)
+    abx.inject_fault(abx.FAULT_LAUNCH, 0)
+    try:
+        with pytest.raises(abx.AbxError) as e:
+            abx.query_nearest(t, q, 8)
+        assert e.value.status == abx.ERR_HIP
+    finally:
+        abx.inject_fault(abx.FAULT_LAUNCH, -1)
+    got = abx.query_nearest(t, q, 8)
+    assert all(torch.equal(a, b) for a, b in zip(want, got))
+
+
+def test_injected_failure_in_one_served_request_leaves_the_others_intact():
+    pts = datagen.shell(50_000, 52, 0.99, 1.01)
+    t = abx.bvh_build(dev(pts), node_format="q16")
+    qs = [datagen.uniform_cube(700, 60 + i, -1.0, 1.0) for i in range(6)]
+    direct = [abx.query_nearest(t, dev(q), 8) for q in qs]
+    torch.cuda.synchronize()
+    s = abx.Server(slots=1, budget_bytes=64 << 20, host_bytes=64 << 20, merge_queries=-1)
+    tid = s.add_tree(t)
+    # the failing launch is the first kernel of one request's sequence; with
+    # one slot and no merging the requests run one after another
+    first = s.submit(tid, abx.REQ_NEAREST, qs[0], k=8)
+    assert s.wait(first)["status"] == abx.OK
+    abx.inject_fault(abx.FAULT_LAUNCH, 0)
+    try:
+        tickets = [s.submit(tid, abx.REQ_NEAREST, q, k=8) for q in qs[1:]]
+        res = [s.wait(tk) for tk in tickets]
+    finally:
+        abx.inject_fault(abx.FAULT_LAUNCH, -1)
+    st = s.stats()
+    s.close()
+    status = [r["status"] for r in res]
+    assert status.count(abx.ERR_HIP) == 1 and status.count(abx.OK) == 4
+    assert st["failed"] == 1
+    for (_, di, dd), r in zip(direct[1:], res):
+        if r["status"] == abx.OK:
+            assert np.array_equal(r["indices"], di.cpu().numpy().reshape(-1))
+            assert np.array_equal(r["distances"], dd.cpu().numpy().reshape(-1))

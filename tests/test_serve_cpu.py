@@ -222,3 +222,58 @@ def test_merged_radius_batches_with_host_backpressure():
     assert st["host_high_water"] <= 96 * 1024 and st["completed"] == 20
     assert st["batches"] < 20
     s.close()
+
+
+def test_injected_launch_failure_fails_one_request_only():
+    # the third batch's launch fails: that request reports ABX_ERR_HIP, the
+    # others complete with their results, and the server keeps serving
+    s = _server(slots=1, budget_bytes=1 << 30, host_bytes=1 << 26, sim_ns_per_query=100)
+    q = np.zeros((300, 3), np.float32)
+    abx.inject_fault(abx.FAULT_LAUNCH, 2)
+    try:
+        tickets = [s.submit(0, abx.REQ_NEAREST, q, k=4) for _ in range(6)]
+        res = [s.wait(t) for t in tickets]
+    finally:
+        abx.inject_fault(abx.FAULT_LAUNCH, -1)
+    status = [r["status"] for r in res]
+    assert status == [abx.OK, abx.OK, abx.ERR_HIP, abx.OK, abx.OK, abx.OK]
+    for r in res:
+        if r["status"] == abx.OK:
+            assert r["offsets"].tolist() == list(range(0, 4 * 301, 4))
+    st = s.stats()
+    assert st["failed"] == 1 and st["completed"] == 5
+    again = s.wait(s.submit(0, abx.REQ_RADIUS, q, radius=0.1))
+    assert again["status"] == abx.OK and again["total"] == 3000
+    s.close()
+
+
+def test_injected_failure_fails_every_member_of_a_merged_batch():
+    s = _server(slots=1, budget_bytes=1 << 30, host_bytes=1 << 26, sim_ns_per_query=2000,
+                merge_queries=1 << 16)
+    q = np.zeros((100, 3), np.float32)
+    first = s.submit(0, abx.REQ_NEAREST, np.zeros((5000, 3), np.float32), k=2)
+    abx.inject_fault(abx.FAULT_LAUNCH, 1)       # the batch after the first one
+    try:
+        tickets = [s.submit(0, abx.REQ_NEAREST, q, k=2) for _ in range(5)]
+        res = [s.wait(t) for t in tickets]
+    finally:
+        abx.inject_fault(abx.FAULT_LAUNCH, -1)
+    assert s.wait(first)["status"] == abx.OK
+    assert all(r["status"] == abx.ERR_HIP for r in res)   # they ran as one batch
+    assert s.stats()["failed"] == 5
+    assert s.wait(s.submit(0, abx.REQ_NEAREST, q, k=2))["status"] == abx.OK
+    s.close()
+
+
+def test_injected_host_allocation_failure():
+    abx.inject_fault(abx.FAULT_HOST_ALLOC, 0)
+    try:
+        with pytest.raises(abx.AbxError) as e:
+            abx.Server(simulate=True, slots=1, budget_bytes=1 << 20, host_bytes=1 << 20)
+        assert e.value.status == abx.ERR_HIP
+    finally:
+        abx.inject_fault(abx.FAULT_HOST_ALLOC, -1)
+    s = _server(slots=1, budget_bytes=1 << 20, host_bytes=1 << 20)   # the next one works
+    s.close()
+    with pytest.raises(abx.AbxError):
+        abx.inject_fault(7, 0)
