@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per load level of the serving block (0: skip it)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
+    ap.add_argument("--serve-slots", type=int, default=4, help="server streams (C5)")
+    ap.add_argument("--serve-merge", type=int, default=0,
+                    help="queries per merged launch (0: the library default, <0: no merging)")
+    ap.add_argument("--serve-small", type=int, default=0,
+                    help="largest request that may be merged (0: the library default)")
     ap.add_argument("--trees", type=int, default=256, help="forest size (C4)")
     ap.add_argument("--paper-sizes", default="1e4,1e5,1e6,1e7",
                     help="m = n sweep of the paper's filled and hollow cases (PAPER)")
@@ -495,7 +500,8 @@ def bench_serving(args, standalone):
         del p
     torch.cuda.synchronize()
     budget = 2 << 30
-    srv = abx.Server(slots=4, budget_bytes=budget, host_bytes=2 << 30)
+    srv = abx.Server(slots=args.serve_slots, budget_bytes=budget, host_bytes=2 << 30,
+                     merge_queries=args.serve_merge, small_queries=args.serve_small)
     tids = [srv.add_tree(t) for t in trees]
     kinds = ("radius", 1, 8, 32)
 
@@ -556,8 +562,11 @@ def bench_serving(args, standalone):
                              "device_p50_ms": round(1e3 * float(np.percentile(gpu_t, 50)), 3),
                              "device_p99_ms": round(1e3 * float(np.percentile(gpu_t, 99)), 3)})
     st = srv.stats()
-    out["server"] = {"slots": 4, "budget_bytes": budget, "max_in_flight": st["max_in_flight"],
-                     "device_high_water": st["device_high_water"], "failed": st["failed"]}
+    out["server"] = {"slots": args.serve_slots, "merge_queries": args.serve_merge,
+                     "small_queries": args.serve_small, "budget_bytes": budget,
+                     "max_in_flight": st["max_in_flight"], "batches": st["batches"],
+                     "requests": st["completed"], "device_high_water": st["device_high_water"],
+                     "failed": st["failed"]}
     out["requests_per_level"] = nreq
     srv.close()
     if standalone:

@@ -252,7 +252,10 @@ def test_injected_failure_fails_every_member_of_a_merged_batch():
                 merge_queries=1 << 16)
     q = np.zeros((100, 3), np.float32)
     first = s.submit(0, abx.REQ_NEAREST, np.zeros((5000, 3), np.float32), k=2)
-    abx.inject_fault(abx.FAULT_LAUNCH, 1)       # the batch after the first one
+    deadline = abx.server_now() + 10.0
+    while s.stats()["in_flight"] == 0 and abx.server_now() < deadline:
+        pass                                    # until the first one has launched
+    abx.inject_fault(abx.FAULT_LAUNCH, 0)       # the next launch: the merged batch
     try:
         tickets = [s.submit(0, abx.REQ_NEAREST, q, k=2) for _ in range(5)]
         res = [s.wait(t) for t in tickets]
