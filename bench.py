@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C3",
-                    choices=["C1", "C2", "C3", "C4", "C5", "COPY", "PAPER"])
+                    choices=["C1", "C2", "C3", "C4", "C5", "COPY", "GATHER", "PAPER"])
     ap.add_argument("--nodes", default="q16", choices=["fp32", "q16", "q16w"])
     ap.add_argument("--morton-bits", type=int, default=21)
     ap.add_argument("--hierarchy", default="karras", choices=["karras", "agglomerative"])
@@ -147,6 +147,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"metric": "device copy", "bytes_read_per_copy": x.numel() * 4,
                           "bytes_written_per_copy": x.numel() * 4, "copies": max(args.steps, 1)}))
+        return
+    if args.workload == "GATHER":
+        # random 32-B row gather from a 1 GiB table: the access pattern of a
+        # node fetch, for scaling HBM counters of random reads
+        rows = 1 << 25
+        table = torch.ones((rows, 8), dtype=torch.int32, device="cuda")
+        idx = torch.randint(0, rows, (1 << 24,), device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+        out = torch.empty((1 << 24, 8), dtype=torch.int32, device="cuda")
+        for _ in range(max(args.steps, 1)):
+            torch.index_select(table, 0, idx, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"metric": "random 32-B row gather", "rows_gathered": idx.numel(),
+                          "bytes_read_per_gather": idx.numel() * (32 + 8),
+                          "bytes_written_per_gather": idx.numel() * 32, "gathers": max(args.steps, 1)}))
         return
     dev = torch.device("cuda:0")
     cfg = datagen.CONFIGS[args.workload]
@@ -439,18 +453,20 @@ def bench_forest(args):
             plan.replay()
         torch.cuda.synchronize()
         abx.timing_reset()
-        # per-kernel times of one eager step with events (graph replays carry none)
+        # per-kernel times of three eager steps with events on the launch
+        # stream (graph replays carry none), per step
         abx.timing_enable(True)
-        plan.build()
-        plan.query()
+        for _ in range(3):
+            plan.build()
+            plan.query()
         torch.cuda.synchronize()
         abx.timing_enable(False)
         ktimes = {}
         for name in ("forest_nearest", "forest_nearest_coop", "refit", "sort_onesweep", "karras",
-                     "forest_keys", "forest_qkeys"):
+                     "forest_keys", "forest_qkeys", "quantise", "forest_boxes"):
             ms, cnt = abx.timing_get(name)
             if cnt:
-                ktimes[name] = round(ms, 4)
+                ktimes[name] = round(ms / 3, 4)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
         ev[0].record()
@@ -461,6 +477,22 @@ def bench_forest(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = ev[0].elapsed_time(ev[1]) / args.steps
+        # algorithmic bytes of the query launch pair: per query the point
+        # (12 B), its order entry (4 B) and its row (8 B per entry), plus
+        # node_b per node visited and 32 B per leaf record read (counting walk)
+        st = plan.stats().cpu().numpy()
+        node_b = 32 if args.nodes == "q16" else 64
+        kk = np.repeat(np.minimum(k, np.diff(off)), np.diff(qoff))
+        alg = int(16 * M + 8 * int(kk.sum()) + node_b * int(st[:, 0].astype(np.int64).sum())
+                  + 32 * int(st[:, 1].astype(np.int64).sum()))
+    pair_ms = ktimes.get("forest_nearest", 0.0) + ktimes.get("forest_nearest_coop", 0.0)
+    achieved = alg / (pair_ms * 1e-3) / 1e9 if pair_ms > 0 else None
+    roof = {"kernel": "forest_nearest+coop", "bound": "hbm",
+            "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+            "bytes_per_launch": alg, "ms_per_launch": round(pair_ms, 4),
+            "visits_per_query": round(float(st[:, 0].mean()), 1)}
+    cpu = None if args.no_cpu_baseline else forest_cpu_baseline(pts_np, off, q_np, qoff, k, args.cpu_seconds)
     return {
         "metric": "forest kNN queries/s (k=16, build + query per step, one HIP graph)",
         "value": round(M / (ms * 1e-3), 1), "unit": "queries/s", "n_gpus": 1,
@@ -474,7 +506,43 @@ def bench_forest(args):
                    "tuned": tuned},
         "eager_kernel_ms": ktimes,
         "results": plan.total,
+        "roofline": roof,
+        **({"cpu_baseline": cpu} if cpu else {}),
     }
+
+
+def forest_cpu_baseline(pts, off, q, qoff, k, budget_s):
+    """The oracle on a seeded sample of the forest's queries: rows drawn
+    evenly from every tree (each answered by brute force over its own tree's
+    points), median of three runs; queries/s."""
+    import oracle
+    oracle.build_library()
+    T = len(off) - 1
+    rng = np.random.default_rng(9)
+
+    def sample(per_tree):
+        return [(t, rng.choice(int(qoff[t + 1] - qoff[t]), min(per_tree, int(qoff[t + 1] - qoff[t])),
+                               replace=False)) for t in range(T)]
+
+    def rate(picks):
+        a = time.perf_counter()
+        cnt = 0
+        for t, rows in picks:
+            if rows.size:
+                oracle.nearest(pts[off[t]:off[t + 1]], oracle.POINTS, q[qoff[t] + rows], k)
+                cnt += rows.size
+        return cnt / (time.perf_counter() - a)
+
+    est = rate(sample(1))
+    per_tree = int(max(1, min(64, est * budget_s / 3 / T)))
+    picks = sample(per_tree)
+    runs = [rate(picks) for _ in range(3)]
+    n_rows = sum(int(r.size) for _, r in picks)
+    return {"value": round(float(np.median(runs)), 2), "unit": "queries/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{n_rows} seeded queries, {per_tree} from each of the {T} trees, each answered by "
+                      f"brute-force k={k} nearest over its own tree; median of 3 runs "
+                      f"({', '.join(f'{x:.1f}' for x in runs)} queries/s)"}
 
 
 def bench_serving(args, standalone):

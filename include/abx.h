@@ -403,6 +403,13 @@ abx_status abx_forest_query_nearest(const abx_forest *f, const abx_forest_querie
                                     const abx_forest_config *cfg, void *scratch, size_t scratch_bytes,
                                     int32_t *offsets /*[M+1]*/, int32_t *indices, float *distances,
                                     abx_stream_t stream);
+/* The same walks in a counting mode (one lane per query throughout, no
+ * results): stats[2*i] = internal nodes visited by query i (caller's
+ * order), stats[2*i+1] = leaf records read; offsets as for the query.  Used
+ * to derive the algorithmic bytes of a forest query. */
+abx_status abx_forest_query_nearest_stats(const abx_forest *f, const abx_forest_queries *q, int32_t k,
+                                          void *scratch, size_t scratch_bytes, int32_t *offsets /*[M+1]*/,
+                                          int32_t *stats /*[2M]*/, abx_stream_t stream);
 /* Times the forest nearest query over a grid of launch shapes (the output
  * buffers are overwritten), keeps the fastest in the handle, writes it to
  * *best and, when json_path is not NULL, appends every timing to that file

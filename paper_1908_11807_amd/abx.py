@@ -163,6 +163,7 @@ def _lib():
                                          vp, vp],
             "abx_forest_autotune": [vp, P(ForestQueries), i32, vp, sz, vp, vp, vp, vp, C.c_char_p,
                                     P(ForestConfig)],
+            "abx_forest_query_nearest_stats": [vp, P(ForestQueries), i32, vp, sz, vp, vp, vp],
             "abx_server_create": [P(ServerConfig), P(vp)],
             "abx_server_add_tree": [vp, vp, P(i32)],
             "abx_server_submit": [vp, P(Request), P(C.c_uint64)],
@@ -595,6 +596,17 @@ class ForestPlan:
     def results(self):
         t = self.total
         return self.offsets, self.indices[:t], self.distances[:t]
+
+    def stats(self):
+        """Per query (node visits, leaf records read), int32 [M, 2], caller's
+        order: the same walks counted, one lane per query."""
+        M = int(self._qoff_h[-1])
+        st = torch.empty((M, 2), dtype=torch.int32, device=self.offsets.device)
+        off = torch.empty(M + 1, dtype=torch.int32, device=self.offsets.device)
+        _check(_lib().abx_forest_query_nearest_stats(self._h, C.byref(self._q), self.k, _ptr(self._qscratch),
+                                                     self._qs, _ptr(off), _ptr(st), _stream()),
+               "abx_forest_query_nearest_stats")
+        return st
 
     def autotune(self, json_path=None):
         best = ForestConfig()

@@ -299,6 +299,27 @@ __attribute__((amdgpu_waves_per_eu(forest_waves_per_eu(K)))) void k_forest_neare
   }
 }
 
+// Counting walk of every tree's queries (node visits and leaf records read,
+// one lane per query throughout, no results): the algorithmic bytes of a
+// forest query.
+template <int KIND, int FMT, int K>
+__global__ __launch_bounds__(kForestBlock) void k_forest_nearest_stats(TreeArgs t, ForestMap map,
+                                                                      const float *__restrict__ pts,
+                                                                      int64_t M,
+                                                                      const int32_t *__restrict__ order,
+                                                                      int32_t *__restrict__ stats) {
+  __shared__ int32_t s_node[kLdsDepthNearest * kForestBlock];
+  __shared__ float s_dist[kLdsDepthNearest * kForestBlock];
+  if (tree_unusable(t)) return;
+  resolve_qframe(t);
+  const int64_t tq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tq >= M) return;
+  ABX_LDS int32_t *ln = (ABX_LDS int32_t *)(s_node) + threadIdx.x;
+  ABX_LDS float *ld = (ABX_LDS float *)(s_dist) + threadIdx.x;
+  nearest_lane<KIND, FMT, K, true, kForestBlock>(t, map, pts, order[tq], ln, ld, nullptr, nullptr, stats,
+                                                 INT64_MAX, HeavyList{});
+}
+
 // ---------------------------------------------------------------- host side
 size_t forest_tree_extra(int T) {
   return align_up((size_t)T * 4, 256) + align_up((size_t)T * 24, 256) + align_up((size_t)(T + 1) * 8, 256);
@@ -403,6 +424,40 @@ abx_status forest_launch_nearest(const TreeArgs &t, int format, const int64_t *p
                                               blocks_per_cu, grab, budget, s);
   return forest_nearest_fmt<ABX_NODES_Q16>(t, map, pts, M, order, k, idx, dist, heavy, counters + 2,
                                            blocks_per_cu, grab, budget, s);
+}
+
+template <int FMT>
+abx_status forest_stats_fmt(const TreeArgs &t, const ForestMap &map, const float *pts, int64_t M,
+                            const int32_t *order, int k, int32_t *stats, hipStream_t s) {
+  const unsigned g = grid_for(M, kForestBlock);
+#define ABX_FS(KK)                                                                                 \
+  return launch("forest_nearest_stats", s, [&] {                                                  \
+    k_forest_nearest_stats<ABX_PRIM_POINTS, FMT, KK><<<g, kForestBlock, 0, s>>>(t, map, pts, M, order, \
+                                                                               stats);              \
+  })
+  if (k <= 1) ABX_FS(1);
+  if (k <= 2) ABX_FS(2);
+  if (k <= 4) ABX_FS(4);
+  if (k <= 8) ABX_FS(8);
+  if (k <= 10) ABX_FS(10);
+  if (k <= 16) ABX_FS(16);
+  if (k <= 32) ABX_FS(32);
+  if (k <= 48) ABX_FS(48);
+  ABX_FS(kMaxRegK);
+#undef ABX_FS
+}
+
+abx_status forest_launch_nearest_stats(const TreeArgs &t, int format, const int64_t *poff,
+                                       const int32_t *qtree, const int32_t *roots, const float *tscene,
+                                       const int32_t *offsets, const float *pts, int64_t M,
+                                       const int32_t *order, int k, int32_t *stats, hipStream_t s) {
+  if (M == 0) return ABX_OK;
+  if (k == 0) return fill_u32(stats, 0, 2 * (size_t)M, s);
+  if (k > kMaxRegK) return ABX_ERR_UNSUPPORTED;
+  const ForestMap map{poff, qtree, roots, tscene, offsets, k};
+  if (format == ABX_NODES_FP32)
+    return forest_stats_fmt<ABX_NODES_FP32>(t, map, pts, M, order, k, stats, s);
+  return forest_stats_fmt<ABX_NODES_Q16>(t, map, pts, M, order, k, stats, s);
 }
 
 int forest_max_trees() { return kForestMaxTrees; }

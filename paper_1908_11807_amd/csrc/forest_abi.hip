@@ -28,6 +28,10 @@ abx_status forest_launch_nearest(const TreeArgs &t, int format, const int64_t *p
                                  const float *pts, int64_t M, const int32_t *order, int k, int32_t *idx,
                                  float *dist, int32_t *heavy_q, float *heavy_bound, uint32_t *counters,
                                  int blocks_per_cu, int grab, int64_t budget, hipStream_t s);
+abx_status forest_launch_nearest_stats(const TreeArgs &t, int format, const int64_t *poff,
+                                       const int32_t *qtree, const int32_t *roots, const float *tscene,
+                                       const int32_t *offsets, const float *pts, int64_t M,
+                                       const int32_t *order, int k, int32_t *stats, hipStream_t s);
 int forest_max_trees();
 // build.hip
 abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
@@ -339,6 +343,38 @@ abx_status abx_forest_query_nearest(const abx_forest *f, const abx_forest_querie
                                reinterpret_cast<float *>(sc + L.heavy_bound),
                                reinterpret_cast<uint32_t *>(sc + L.counters), c.blocks_per_cu,
                                c.tiles_per_grab, c.budget > 0 ? c.budget : INT64_MAX, s);
+}
+
+abx_status abx_forest_query_nearest_stats(const abx_forest *f, const abx_forest_queries *q, int32_t k,
+                                          void *scratch, size_t scratch_bytes, int32_t *offsets,
+                                          int32_t *stats, abx_stream_t stream) {
+  int64_t tot = 0;
+  ABX_TRY(forest_query_check(f, q, k, &tot));
+  if (k > kMaxRegK) return ABX_ERR_UNSUPPORTED;
+  const int T = f->T;
+  const int64_t M = q->offsets_host[T];
+  const ForestQueryLayout L = forest_query_layout(T, M);
+  if (!scratch || scratch_bytes < L.bytes || !aligned256(scratch) || !offsets) return ABX_ERR_INVALID_ARG;
+  if (M > 0 && !stats) return ABX_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *sc = static_cast<char *>(scratch);
+  const int64_t *poff = reinterpret_cast<const int64_t *>(f->tree + f->L.offs);
+  const float *tscene = reinterpret_cast<const float *>(f->tree + f->L.tscene);
+  const int32_t *roots = reinterpret_cast<const int32_t *>(f->tree + f->L.roots);
+  int32_t *order = reinterpret_cast<int32_t *>(sc + L.order);
+  int32_t *qtree = reinterpret_cast<int32_t *>(sc + L.qtree);
+  ABX_TRY(forest_launch_qkeys(q->data, M, q->offsets_dev, T, tscene, reinterpret_cast<uint64_t *>(sc + L.keys),
+                              qtree, s));
+  ABX_TRY(radix_sort(sc + L.keys, nullptr, M, kForestQueryKeyBits, sc + L.sorted, order, sc + L.sort,
+                     radix_sort_scratch_bytes(M, kForestQueryKeyBits), s));
+  ABX_TRY(order_guard(radix_sort_err_word(sc + L.sort, M, kForestQueryKeyBits), order, M, s));
+  ABX_TRY(forest_launch_rows(poff, q->offsets_dev, qtree, M, T, k, reinterpret_cast<int64_t *>(sc + L.base),
+                             offsets, s));
+  if (M == 0) return ABX_OK;
+  if (f->N == 0) return fill_u32(stats, 0, 2 * (size_t)M, s);
+  const TreeArgs t = forest_tree_args(f);
+  return forest_launch_nearest_stats(t, f->format, poff, qtree, roots, tscene, offsets, q->data, M, order,
+                                     k, stats, s);
 }
 
 abx_status abx_forest_autotune(abx_forest *f, const abx_forest_queries *q, int32_t k, void *scratch,

@@ -133,3 +133,22 @@ def test_forest_k_above_64_unsupported():
     with pytest.raises(abx.AbxError) as e:
         plan.query()
     assert e.value.status == abx.ERR_UNSUPPORTED
+
+
+def test_forest_stats_count_the_walks():
+    # the counting walk: every query with a tree of two or more points visits
+    # at least the root; point trees read no leaf records; an empty tree's
+    # queries count nothing
+    sizes = [0, 1, 2, 50, 3000, 777]
+    qsizes = [4, 5, 6, 100, 200, 50]
+    pts, off, qs, qoff = make_forest(31, sizes, qsizes)
+    plan = abx.ForestPlan(torch.from_numpy(pts).cuda(), off, torch.from_numpy(qs).cuda(), qoff, 10, "q16")
+    plan.check()
+    st = plan.stats().cpu().numpy()
+    assert st.shape == (int(qoff[-1]), 2)
+    assert np.all(st[:, 1] == 0)
+    tree = np.repeat(np.arange(len(sizes)), qsizes)
+    n_t = np.array(sizes)[tree]
+    assert np.all(st[n_t <= 1, 0] == 0)
+    assert np.all(st[n_t >= 2, 0] >= 1)
+    assert np.all(st[n_t >= 2, 0] <= np.maximum(n_t[n_t >= 2] - 1, 1))
