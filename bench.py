@@ -57,9 +57,10 @@ def parse():
 
 
 def measured_traffic(kernel, workload, nodes, k):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), or None when no
-    summary covers this launch or the kernel sources changed since."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary:
+    (copy-calibrated FETCH_SIZE x 2.0 + WRITE_SIZE, raw FETCH_SIZE + WRITE_SIZE,
+    source file), or Nones when no summary covers this launch or the kernel
+    sources changed since."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
@@ -73,9 +74,11 @@ def measured_traffic(kernel, workload, nodes, k):
             with open(os.path.join(ROOT, src), "rb") as f:
                 h.update(f.read())
         if h.hexdigest() != rec["sources_sha256"]:
-            return None, None
-        return int(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
-    return None, None
+            return None, None, None
+        raw = rec.get("traffic_bytes_per_launch_raw")
+        return (int(rec["traffic_bytes_per_launch"]), None if raw is None else int(raw),
+                os.path.relpath(path, ROOT))
+    return None, None, None
 
 
 def algorithmic_bytes(stats, node_b, leaf_b, per_query_fixed):
@@ -254,10 +257,17 @@ def main():
     if dom in alg:
         per_launch = alg[dom]
         achieved = per_launch / (ktimes[dom]["ms_per_launch"] * 1e-3) / 1e9
-        traffic, tsrc = measured_traffic(dom, args.workload, args.nodes, k)
+        traffic, traffic_raw, tsrc = measured_traffic(dom, args.workload, args.nodes, k)
         roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    traffic_source=tsrc, bytes_per_launch=per_launch,
+                    traffic_raw=traffic_raw, traffic_source=tsrc,
+                    # the measured DRAM bytes over the same launch time: the HBM
+                    # fraction the counters support (copy-calibrated and raw)
+                    traffic_frac=None if traffic is None else round(
+                        traffic / (ktimes[dom]["ms_per_launch"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    traffic_raw_frac=None if traffic_raw is None else round(
+                        traffic_raw / (ktimes[dom]["ms_per_launch"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    bytes_per_launch=per_launch,
                     ms_per_launch=round(ktimes[dom]["ms_per_launch"], 4))
     else:
         roof = dict(kernel=dom, bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s",

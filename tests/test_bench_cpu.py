@@ -63,17 +63,20 @@ def test_committed_traffic_records():
         if not os.path.exists(path):
             pytest.skip(f"no traffic record for {nodes}")
         rec = json.load(open(path))
-        traffic, src = bench.measured_traffic("nearest+coop", "C3", nodes, 10)
+        traffic, raw, src = bench.measured_traffic("nearest+coop", "C3", nodes, 10)
         if _sources_hash(ROOT, rec["sources"]) != rec["sources_sha256"]:
-            assert (traffic, src) == (None, None)
+            assert (traffic, raw, src) == (None, None, None)
             continue
         assert src == os.path.relpath(path, ROOT)
         assert traffic == rec["traffic_bytes_per_launch"]
         # the figure is the copy-calibrated counters, as recorded
-        kib = sum(rec["fetch_kib_per_launch"].values()) * rec["fetch_scale"] + \
-            sum(rec["write_kib_per_launch"].values()) * rec["write_scale"]
+        fetch = sum(rec["fetch_kib_per_launch"].values())
+        write = sum(rec["write_kib_per_launch"].values())
+        kib = fetch * rec["fetch_scale"] + write * rec["write_scale"]
         assert abs(traffic - 1024 * kib) <= 1
-    assert bench.measured_traffic("nearest+coop", "C3", "q16", 11) == (None, None)
+        if raw is not None:
+            assert abs(raw - 1024 * (fetch + write)) <= 1
+    assert bench.measured_traffic("nearest+coop", "C3", "q16", 11) == (None, None, None)
 
 
 def test_traffic_record_is_dropped_when_sources_change(tmp_path, monkeypatch):
@@ -88,11 +91,11 @@ def test_traffic_record_is_dropped_when_sources_change(tmp_path, monkeypatch):
     (tmp_path / "profiles" / "traffic_x.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic("nearest+coop", "C3", "q16", 10) == \
-        (123456789, os.path.join("profiles", "traffic_x.json"))
-    assert bench.measured_traffic("nearest+coop", "C3", "fp32", 10) == (None, None)
+        (123456789, None, os.path.join("profiles", "traffic_x.json"))
+    assert bench.measured_traffic("nearest+coop", "C3", "fp32", 10) == (None, None, None)
     with open(tmp_path / sources[0], "a") as f:
         f.write("// edited\n")
-    assert bench.measured_traffic("nearest+coop", "C3", "q16", 10) == (None, None)
+    assert bench.measured_traffic("nearest+coop", "C3", "q16", 10) == (None, None, None)
 
 
 def test_cpu_baseline_reports_the_oracle_rate():
