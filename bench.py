@@ -89,10 +89,12 @@ def algorithmic_bytes(stats, node_b, leaf_b, per_query_fixed):
 
 
 def build_bytes_per_prim(node_format, morton_bits, kind_width=3, depth_first=False, wide_per_prim=0.0):
-    """Algorithmic bytes of one build, per point primitive (chunked refit,
-    8-bit radix digits; `depth_first`: the tree's nodes were renumbered in
-    depth-first order, which Q16 Karras trees of 2^22 primitives and more
-    get by default; `wide_per_prim`: 4-wide nodes written per primitive)."""
+    """Algorithmic bytes of one Karras build, per point primitive (8-bit radix
+    digits; `depth_first`: the tree's nodes were renumbered in depth-first
+    order, which Q16 Karras trees of 2^22 primitives and more get by default;
+    `wide_per_prim`: 4-wide nodes written per primitive).  The refit writes
+    each node once, in its final format; its chunk-crossing staging (a few
+    per cent of the nodes) is not counted."""
     keyb = 8 if morton_bits > 10 else 4          # 63- or 30-bit Morton keys
     passes = 8 if morton_bits > 10 else 4        # 8-bit digits
     w = 4 * kind_width                           # 12 B point (24 B box)
@@ -100,24 +102,27 @@ def build_bytes_per_prim(node_format, morton_bits, kind_width=3, depth_first=Fal
     b += w + keyb + 4                            # Morton: read, write key and index
     b += keyb                                    # digit histograms: read the keys once
     b += passes * 2 * (keyb + 4)                 # onesweep passes: read and write (key, index)
-    b += keyb + 8 + 8                            # hierarchy: keys, child refs, parent + range end
-    b += 4 + w + 4                               # refit, leaf: permutation, primitive, parent
-    b += 4 + 4 + 64 + 28                         # refit, node: parent, range end, node, sibling
+    b += keyb + 8 + 8 + 4 + 4                    # hierarchy: keys; parent words of the leaf
+    #                                              and the node, range end, arrival counter
+    ordered = node_format == "q16w" or (node_format == "q16" and depth_first)
+    if ordered:
+        b += 8 + 8                               # depth-first order: parent word, first word
+        b += 6 * (8 + 8 + 8)                     # 6 pointer-jumping rounds: own, ancestor's, out
+        b += 8 + 8 + 4 + 4                       # last round: words, range end, the index
+        if node_format == "q16w":
+            b += 4                               # and the depth
+    b += 4 + 8 + w                               # refit, leaf: permutation, parent word, primitive
+    b += 8                                       # refit, node: parent word
+    if node_format == "q16":
+        b += (4 if depth_first else 0) + 32      # its depth-first slot, the Q16 node
+    else:
+        b += 64                                  # the FP32 node (staged, for 4-wide trees)
     if node_format == "q16w":
-        b += 4 + 8 + 6 * (8 + 8 + 8)             # depth and order: init, 6 pointer-jumping rounds
-        b += 8 + 8 + 4 + 4 + 4                   # last round: words, range end, index and depth
         b += 4 + 4 + 4                           # flags: index, depth, flag
         b += 4 + 4                               # scan of the flags
         b += 64 + 4 + 4 + 4 + 4                  # collapse: every binary node read once, its depth,
         #                                          index, rank, and its rank read by its parent
         b += 64 * wide_per_prim                  # the 4-wide nodes written
-    if node_format == "q16":
-        b += 64 + 32                             # quantise: read FP32 node, write Q16 node
-        if depth_first:
-            b += 4 + 8                           # depth-first order: parent link, first word
-            b += 6 * (8 + 8 + 8)                 # 6 pointer-jumping rounds: own, ancestor's, out
-            b += 8 + 8 + 4 + 4                   # last round: words, range end, the index
-            b += 4 + 8                           # quantise: its own and its children's index
     return b
 
 

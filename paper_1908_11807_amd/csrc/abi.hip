@@ -18,22 +18,20 @@ abx_status launch_scene(int kind, const float *prims, int64_t n, float *partial,
 int scene_blocks(int64_t n);
 abx_status launch_morton(int kind, const float *prims, int64_t n, const float *scene, int bits,
                          void *codes, bool wide, hipStream_t s);
-abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
-                         int32_t *parent_leaf, int32_t *parent_int, int32_t *other_end,
-                         uint32_t *flags, const TreeHeader *hdr, hipStream_t s);
+abx_status launch_karras(bool wide, const void *keys, int64_t n, uint64_t *pw_leaf, uint64_t *pw_int,
+                         int32_t *other_end, uint32_t *flags, const TreeHeader *hdr, hipStream_t s);
 abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
-                        const int32_t *parent_leaf, const int32_t *parent_int,
-                        const int32_t *other_end, NodeF32 *nodes, uint32_t *flags,
-                        TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
-                        uint32_t *frontier_count, hipStream_t s);
-size_t refit_frontier_cap(int64_t n);
+                        const uint64_t *pw_leaf, const uint64_t *pw_int, const int32_t *pre,
+                        void *out, NodeF32 *stage, uint32_t *flags, TreeHeader *hdr, void *box_rec,
+                        void *lists_mem, hipStream_t s);
+size_t refit_lists_bytes(int64_t n);
 abx_status launch_agglo(bool wide, int kind, bool q16, const void *keys, const float *prims,
                         const int32_t *perm, int64_t n, NodeF32 *nodes, int32_t *range_lo,
                         int32_t *range_hi, uint32_t *flags, TreeHeader *hdr, void *q16_leaves,
                         int32_t *frontier, uint32_t *frontier_count, hipStream_t s);
 abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, TreeHeader *hdr,
                            const int32_t *pre, NodeQ16 *dst, hipStream_t s);
-abx_status launch_preorder(const int32_t *parent_int, const int32_t *other_end, int64_t ni,
+abx_status launch_preorder(const uint64_t *pw_int, const int32_t *other_end, int64_t ni,
                            uint64_t *work, int32_t *pre, int32_t *depth, hipStream_t s);
 abx_status launch_wide(int kind, const NodeF32 *src, int64_t ni, const int32_t *pre,
                        const int32_t *depth, int32_t *flag, int32_t *rank, int64_t *d_total,
@@ -180,16 +178,16 @@ BuildLayout build_layout(const abx_primitives *p, const abx_build_options *o) {
   off = align_up(off + n * ksz, 256);
   L.perm = off;
   off = align_up(off + (L.boxrec ? n * 4 : 0), 256);
-  L.parent_leaf = off;
-  off = align_up(off + n * 4, 256);
+  L.parent_leaf = off;  // parent words (the agglomerative build: range ends)
+  off = align_up(off + n * 8, 256);
   L.parent_int = off;
-  off = align_up(off + n * 4, 256);
+  off = align_up(off + n * 8, 256);
   L.other_end = off;
   off = align_up(off + n * 4, 256);
   L.flags = off;
   off = align_up(off + n * 4, 256);
   L.frontier = off;
-  off = align_up(off + 256 + refit_frontier_cap(L.n) * 4, 256);
+  off = align_up(off + refit_lists_bytes(L.n), 256);
   L.staging = off;
   off = align_up(off + (L.q16 ? (size_t)L.ni * sizeof(NodeF32) : 0), 256);
   L.pre = off;  // depth-first order: two buffers of 64-bit pointer-jumping words, the index
@@ -461,8 +459,8 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
                            : reinterpret_cast<int32_t *>(tree + L.leaves_off);
   NodeF32 *fnodes = L.q16 ? reinterpret_cast<NodeF32 *>(sc + L.staging)
                           : reinterpret_cast<NodeF32 *>(tree + L.nodes_off);
-  int32_t *parent_leaf = reinterpret_cast<int32_t *>(sc + L.parent_leaf);
-  int32_t *parent_int = reinterpret_cast<int32_t *>(sc + L.parent_int);
+  uint64_t *pw_leaf = reinterpret_cast<uint64_t *>(sc + L.parent_leaf);
+  uint64_t *pw_int = reinterpret_cast<uint64_t *>(sc + L.parent_int);
   int32_t *other_end = reinterpret_cast<int32_t *>(sc + L.other_end);
   uint32_t *flags = reinterpret_cast<uint32_t *>(sc + L.flags);
   if (n > 0) {
@@ -471,40 +469,43 @@ abx_status abx_bvh_build(const abx_primitives *prims, const abx_build_options *o
     ABX_TRY(radix_sort(sc + L.codes, nullptr, n, 3 * L.bits, sc + L.sorted, perm, sc + L.sort,
                        radix_sort_scratch_bytes(n, 3 * L.bits), s,
                        reinterpret_cast<uint32_t *>(&hdr->bad), kBadSort));
-    uint32_t *fcount = reinterpret_cast<uint32_t *>(sc + L.frontier);
-    int32_t *frontier = reinterpret_cast<int32_t *>(sc + L.frontier + 256);
+    void *box_rec = L.boxrec ? tree + L.leaves_off : nullptr;
     if (agglo) {
-      // range ends of the agglomerative climb reuse the parent arrays
+      uint32_t *fcount = reinterpret_cast<uint32_t *>(sc + L.frontier);
+      int32_t *frontier = reinterpret_cast<int32_t *>(sc + L.frontier + 256);
+      // range ends of the agglomerative climb reuse the parent-word arrays
       ABX_TRY(launch_agglo(L.wide, kind, L.q16, sc + L.sorted, prims->data, perm, n, fnodes,
-                           parent_leaf, parent_int, flags, hdr, tree + L.leaves_off, frontier,
-                           fcount, s));
-    }
-    int32_t *pre = nullptr;
-    if (!agglo) {
-      ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, fnodes, parent_leaf, parent_int, other_end,
-                            flags, hdr, s));
-      ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, parent_leaf, parent_int, other_end,
-                           fnodes, flags, hdr, tree + L.leaves_off, frontier, fcount, s));
-      // depth-first order of the Q16 nodes (written by the quantisation);
-      // run beside the refit on a second stream it saved 0.04 ms of 0.4 at
-      // 1e7 (the two share the GPU), so it stays on the caller's stream
+                           reinterpret_cast<int32_t *>(pw_leaf), reinterpret_cast<int32_t *>(pw_int),
+                           flags, hdr, box_rec, frontier, fcount, s));
+      if (L.q16)
+        ABX_TRY(launch_quantise(kind, fnodes, L.ni, hdr, nullptr,
+                                reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
+    } else {
+      ABX_TRY(launch_karras(L.wide, sc + L.sorted, n, pw_leaf, pw_int, other_end, flags, hdr, s));
+      // depth-first order first: the refit writes each node at its final slot
+      int32_t *pre = nullptr, *depth = nullptr;
       if (L.preorder || L.wnodes) {
         uint64_t *work = reinterpret_cast<uint64_t *>(sc + L.pre);
         pre = reinterpret_cast<int32_t *>(work + 2 * L.ni);
-        int32_t *depth = L.wnodes ? reinterpret_cast<int32_t *>(sc + L.wbuf) : nullptr;
-        ABX_TRY(launch_preorder(parent_int, other_end, L.ni, work, pre, depth, s));
-        if (L.wnodes) {
-          int32_t *flag = depth + L.ni, *rank = flag + L.ni;
-          char *tail = sc + L.wbuf + align_up(3 * (size_t)L.ni * 4 + 4, 256);
-          ABX_TRY(launch_wide(kind, fnodes, L.ni, pre, depth, flag, rank,
-                              reinterpret_cast<int64_t *>(tail), tail + 256, scan_scratch_bytes(L.ni),
-                              hdr, reinterpret_cast<NodeW *>(tree + L.nodes_off), s));
-        }
+        depth = L.wnodes ? reinterpret_cast<int32_t *>(sc + L.wbuf) : nullptr;
+        ABX_TRY(launch_preorder(pw_int, other_end, L.ni, work, pre, depth, s));
+      }
+      if (L.wnodes) {
+        // 4-wide nodes are collapsed from the FP32 binary tree in build order
+        ABX_TRY(launch_refit(kind, false, prims->data, perm, n, pw_leaf, pw_int, nullptr, fnodes,
+                             fnodes, flags, hdr, box_rec, sc + L.frontier, s));
+        int32_t *flag = depth + L.ni, *rank = flag + L.ni;
+        char *tail = sc + L.wbuf + align_up(3 * (size_t)L.ni * 4 + 4, 256);
+        ABX_TRY(launch_wide(kind, fnodes, L.ni, pre, depth, flag, rank,
+                            reinterpret_cast<int64_t *>(tail), tail + 256, scan_scratch_bytes(L.ni),
+                            hdr, reinterpret_cast<NodeW *>(tree + L.nodes_off), s));
+      } else {
+        // Q16 nodes are written directly (FP32 records of chunk-crossing
+        // nodes wait in the staging area); FP32 nodes stage in place
+        ABX_TRY(launch_refit(kind, L.q16, prims->data, perm, n, pw_leaf, pw_int, pre,
+                             tree + L.nodes_off, fnodes, flags, hdr, box_rec, sc + L.frontier, s));
       }
     }
-    if (L.q16 && !L.wnodes)
-      ABX_TRY(launch_quantise(kind, fnodes, L.ni, hdr, pre,
-                              reinterpret_cast<NodeQ16 *>(tree + L.nodes_off), s));
   }
   TreeHeader h;
   ABX_HIP(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -193,6 +193,14 @@ __global__ __launch_bounds__(kBuildBlock) void k_morton(const float *__restrict_
     codes[i] = (K)((spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]));
 }
 
+// A node's parent word: parent << 1 | side in the low half, the far end j of
+// the parent's leaf range [min(parent, j), max(parent, j)] in the high half,
+// so one load names the next node of a climb and whether its range leaves the
+// current chunk or group.
+__device__ __forceinline__ uint64_t parent_word(int64_t parent, int side, int64_t j) {
+  return ((uint64_t)(uint32_t)j << 32) | (uint32_t)((parent << 1) | side);
+}
+
 // ------------------------------------------------------------ Karras 2012
 // Common-prefix length of the index-augmented codes at sorted positions i
 // and j (-1 outside [0, n)).  Equal codes fall back to the positions, which
@@ -210,14 +218,14 @@ __device__ __forceinline__ int delta(const K *__restrict__ keys, int64_t n, int6
 // One thread per internal node i: direction from the neighbours, range end
 // by exponential then binary search, split by binary search on the prefix,
 // children at gamma / gamma+1 (leaf when the child range has one element).
-// Writes the two child references, the parents (parent<<1 | side), the far
-// end j of the node's range [min(i,j), max(i,j)] and clears the node's
-// arrival counter.
+// Writes the children's parent words (parent << 1 | side, and the far end j
+// of this node's range [min(i,j), max(i,j)]), its own range end and clears
+// its arrival counter.  The child references are written by the refit, which
+// emits each node whole.
 template <typename K>
 __global__ __launch_bounds__(kBuildBlock) void k_karras(const K *__restrict__ keys, int64_t n,
-                                                        NodeF32 *__restrict__ nodes,
-                                                        int32_t *__restrict__ parent_leaf,
-                                                        int32_t *__restrict__ parent_int,
+                                                        uint64_t *__restrict__ pw_leaf,
+                                                        uint64_t *__restrict__ pw_int,
                                                         int32_t *__restrict__ other_end,
                                                         uint32_t *__restrict__ flags,
                                                         const TreeHeader *__restrict__ hdr) {
@@ -243,17 +251,14 @@ __global__ __launch_bounds__(kBuildBlock) void k_karras(const K *__restrict__ ke
   const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
   const int64_t first = i < j ? i : j, last = i < j ? j : i;
   const bool left_leaf = first == gamma, right_leaf = last == gamma + 1;
-  const int32_t lref = left_leaf ? ~(int32_t)gamma : (int32_t)gamma;
-  const int32_t rref = right_leaf ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
-  nodes[i].d = make_int4(lref, rref, 0, 0);
-  const int32_t pl = (int32_t)(i << 1), pr = (int32_t)((i << 1) | 1);
-  if (left_leaf) parent_leaf[gamma] = pl; else parent_int[gamma] = pl;
-  if (right_leaf) parent_leaf[gamma + 1] = pr; else parent_int[gamma + 1] = pr;
+  const uint64_t pl = parent_word(i, 0, j), pr = parent_word(i, 1, j);
+  if (left_leaf) pw_leaf[gamma] = pl; else pw_int[gamma] = pl;
+  if (right_leaf) pw_leaf[gamma + 1] = pr; else pw_int[gamma + 1] = pr;
   other_end[i] = (int32_t)j;
   flags[i] = 0;
 }
 
-// ------------------------------------------------------------ bottom-up refit
+// ------------------------------------------------------------ FP32 child slots
 __device__ __forceinline__ void store_child(NodeF32 *node, int side, const float b[6], int h) {
   float *f = reinterpret_cast<float *>(node);
   const int o = side * 6;
@@ -270,112 +275,12 @@ __device__ __forceinline__ void load_child(const NodeF32 *node, int side, float 
   h = reinterpret_cast<const int *>(node)[14 + side];
 }
 
-// Bottom-up refit in two launches.  One thread per leaf climbs from its
-// leaf: at each parent it writes its box into its child slot, then counts
-// its arrival; the first arrival stops, the second unions both children and
-// climbs on.  The leaf's thread also rewrites its parent's reference to the
-// leaf from the sorted position to ~(primitive index), and for Q16 box trees
-// writes the exact box record.
-//
-// Phase 1: each workgroup owns a chunk of kRefitChunk consecutive leaves (in
-// sorted order).  An internal node whose leaf range lies inside the chunk has
-// both children climbed by threads of the same workgroup, so the hand-off is
-// synchronised at workgroup scope (arrival counter in LDS; the sibling's box
-// is read back from the node in global memory, ordered by the counter's
-// acquire-release).  A thread that reaches a node whose range crosses the
-// chunk boundary stops there and appends (node, side) to the frontier list.
-// Phase 2 (one workgroup per 64 chunks) climbs the crossing nodes inside its
-// 64 chunks; phase 3 (one workgroup) the few that cross those groups.  Each
-// phase starts after a kernel boundary has made the previous one's stores
-// visible and synchronises at workgroup scope.  No step needs agent-scope
-// fences (which would write back and invalidate the XCDs' L2s).
+// Chunking of the agglomerative build's bottom-up pass (below).
 constexpr int kRefitThreads = 1024;
 constexpr int kRefitPerThread = 8;
 constexpr int kRefitChunk = kRefitThreads * kRefitPerThread;
 constexpr int kRefitMaxSteps = 256;  // > any tree height; only bounds the loops
-
-template <int KIND, bool kQ16>
-__global__ __launch_bounds__(kRefitThreads) void k_refit_local(
-    const float *__restrict__ prims, const int32_t *__restrict__ perm, int64_t n,
-    const int32_t *__restrict__ parent_leaf, const int32_t *__restrict__ parent_int,
-    const int32_t *__restrict__ other_end, NodeF32 *nodes, TreeHeader *hdr, void *q16_leaves,
-    int32_t *__restrict__ frontier, uint32_t *__restrict__ frontier_count, uint32_t frontier_cap) {
-  // after a failed sort the permutation and hierarchy are not valid: the
-  // whole grid exits (the frontier stays empty, so the later phases do too)
-  if (hdr->bad & kBadSort) return;
-  __shared__ uint32_t s_cnt[kRefitChunk];
-  for (int i = threadIdx.x; i < kRefitChunk; i += kRefitThreads) s_cnt[i] = 0;
-  __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * kRefitChunk;
-  for (int r = 0; r < kRefitPerThread; ++r) {
-    const int64_t p = c0 + (int64_t)r * kRefitThreads + threadIdx.x;
-    if (p >= n) return;
-    const int32_t orig = perm[p];
-    float b[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      b[a] = KIND == ABX_PRIM_POINTS ? prims[3 * (int64_t)orig + a] : prims[6 * (int64_t)orig + a];
-      b[3 + a] = KIND == ABX_PRIM_POINTS ? b[a] : prims[6 * (int64_t)orig + 3 + a];
-    }
-    if (kQ16 && KIND == ABX_PRIM_BOXES) {
-      // exact box record of a Q16 box tree, addressed by primitive index
-      float4 *o = reinterpret_cast<float4 *>(q16_leaves) + 2 * (int64_t)orig;
-      o[0] = make_float4(b[0], b[1], b[2], b[3]);
-      o[1] = make_float4(b[4], b[5], __int_as_float((int32_t)p), 0.0f);
-    }
-    if (n == 1) return;
-    int h = 0;
-    int32_t pp = parent_leaf[p];
-    // the parent's reference to this leaf names the primitive itself
-    reinterpret_cast<int32_t *>(nodes + (pp >> 1))[12 + (pp & 1)] = ~orig;
-    int64_t j = other_end[pp >> 1];
-    for (int step = 0; step < kRefitMaxSteps; ++step) {
-      const int32_t parent = pp >> 1, side = pp & 1;
-      // The climb is a chain of dependent reads.  The hierarchy arrays are
-      // read-only here, so the next parent is fetched before this level's
-      // hand-off and the next range end while the sibling's box is read:
-      // one exposed memory latency per level instead of three.
-      const int32_t up = parent_int[parent];
-      store_child(nodes + parent, side, b, h);
-      const int64_t f = parent < j ? parent : j, l = parent < j ? j : parent;
-      if (f < c0 || l >= c0 + kRefitChunk) {
-        const uint32_t e = atomicAdd(frontier_count, 1u);
-        if (e < frontier_cap) frontier[e] = pp;
-        else atomicOr(&hdr->bad, 4);
-        break;
-      }
-      const uint32_t old = __hip_atomic_fetch_add(&s_cnt[parent - c0], 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (old == 0) break;
-      float sb[6];
-      int sh;
-      load_child(nodes + parent, side ^ 1, sb, sh);
-      const int64_t jn = parent != 0 ? other_end[up >> 1] : 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        b[a] = fminf(b[a], sb[a]);
-        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
-      }
-      h = (h > sh ? h : sh) + 1;
-      if (parent == 0) {
-        hdr->height = h;
-        break;
-      }
-      pp = up;
-      j = jn;
-      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
-    }
-  }
-}
-
-// Phase 2: one workgroup per super-chunk of kMidChunks chunks climbs the
-// chunk-crossing nodes whose leaf range lies inside its super-chunk.  All
-// arrivals at such a node come from that workgroup (from its own entries or
-// its own climbs), so workgroup-scope counters in global memory suffice.  A
-// climb that reaches a node crossing a super-chunk boundary stores its box
-// there and hands (node, side) to the last phase.  Entries are routed by the
-// super-chunk holding the first leaf of the node's range; each workgroup
-// reads the whole list in unrolled batches, so the reads overlap.
+// its middle pass: one workgroup per kMidChunks chunks
 constexpr int kMidChunks = 64;
 constexpr int64_t kMidLeaves = (int64_t)kRefitChunk * kMidChunks;
 // A crossing node inside a super-chunk is an ancestor of the split at one of
@@ -383,130 +288,6 @@ constexpr int64_t kMidLeaves = (int64_t)kRefitChunk * kMidChunks;
 // (kMidChunks - 1) * (tree height, < 96 for 63-bit keys augmented by 31-bit
 // positions) of them, each with at most two entries.
 constexpr int kMidListCap = 2 * kMidChunks * 96;
-
-__global__ __launch_bounds__(kRefitThreads) void k_refit_mid(
-    const int32_t *__restrict__ parent_int, const int32_t *__restrict__ other_end, NodeF32 *nodes,
-    uint32_t *flags, TreeHeader *hdr, const int32_t *__restrict__ fa,
-    const uint32_t *__restrict__ fa_count, int32_t *__restrict__ fb, uint32_t *__restrict__ fb_count,
-    uint32_t cap) {
-  __shared__ int32_t s_list[kMidListCap];
-  __shared__ uint32_t s_n;
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  const uint32_t cnt = min(*fa_count, cap);
-  const int64_t s0 = (int64_t)blockIdx.x * kMidLeaves, s1 = s0 + kMidLeaves;
-  constexpr int kBatch = 8;
-  for (uint32_t e0 = threadIdx.x; e0 < cnt; e0 += kBatch * kRefitThreads) {
-    int32_t pp[kBatch], j[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const uint32_t e = e0 + (uint32_t)u * kRefitThreads;
-      pp[u] = e < cnt ? fa[e] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) j[u] = pp[u] >= 0 ? other_end[pp[u] >> 1] : 0;
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      if (pp[u] < 0) continue;
-      const int64_t p = pp[u] >> 1;
-      const int64_t f = p < j[u] ? p : j[u], l = p < j[u] ? j[u] : p;
-      if (f < s0 || f >= s1) continue;  // another super-chunk's entry
-      if (l >= s1) {
-        const uint32_t e = atomicAdd(fb_count, 1u);
-        if (e < cap) fb[e] = pp[u];
-        else atomicOr(&hdr->bad, 4);
-      } else {
-        const uint32_t e = atomicAdd(&s_n, 1u);
-        if (e < (uint32_t)kMidListCap) s_list[e] = pp[u];
-      }
-    }
-  }
-  __syncthreads();
-  const uint32_t own = min(s_n, (uint32_t)kMidListCap);
-  if (threadIdx.x == 0 && s_n > (uint32_t)kMidListCap) atomicOr(&hdr->bad, 4);
-  for (uint32_t e = threadIdx.x; e < own; e += kRefitThreads) {
-    int32_t pp = s_list[e];
-    int32_t parent = pp >> 1, side = pp & 1;
-    float b[6];
-    int h;
-    load_child(nodes + parent, side, b, h);
-    for (int step = 0; step < kRefitMaxSteps; ++step) {
-      const int32_t up = parent_int[parent];  // read-only: overlaps the hand-off
-      const uint32_t old = __hip_atomic_fetch_add(flags + parent, 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (old == 0) break;
-      float sb[6];
-      int sh;
-      load_child(nodes + parent, side ^ 1, sb, sh);
-      const int64_t jn = parent != 0 ? other_end[up >> 1] : 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        b[a] = fminf(b[a], sb[a]);
-        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
-      }
-      h = (h > sh ? h : sh) + 1;
-      if (parent == 0) {
-        hdr->height = h;
-        break;
-      }
-      pp = up;
-      parent = pp >> 1;
-      side = pp & 1;
-      store_child(nodes + parent, side, b, h);
-      const int64_t f = parent < jn ? parent : jn, l = parent < jn ? jn : parent;
-      if (f < s0 || l >= s1) {
-        const uint32_t e2 = atomicAdd(fb_count, 1u);
-        if (e2 < cap) fb[e2] = pp;
-        else atomicOr(&hdr->bad, 4);
-        break;
-      }
-      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
-    }
-  }
-}
-
-// Phase 3: one workgroup climbs the nodes that cross super-chunk boundaries.
-// The arrival counters are the global `flags` (cleared by the hierarchy
-// kernel); every hand-off is between threads of this one workgroup.
-__global__ __launch_bounds__(kRefitThreads) void k_refit_top(const int32_t *__restrict__ parent_int,
-                                                             NodeF32 *nodes, uint32_t *flags,
-                                                             TreeHeader *hdr,
-                                                             const int32_t *__restrict__ frontier,
-                                                             const uint32_t *__restrict__ frontier_count,
-                                                             uint32_t frontier_cap) {
-  const uint32_t cnt = min(*frontier_count, frontier_cap);
-  for (uint32_t e = threadIdx.x; e < cnt; e += kRefitThreads) {
-    int32_t pp = frontier[e];
-    int32_t parent = pp >> 1, side = pp & 1;
-    float b[6];
-    int h;
-    load_child(nodes + parent, side, b, h);
-    for (int step = 0; step < kRefitMaxSteps; ++step) {
-      const int32_t up = parent_int[parent];  // read-only: overlaps the hand-off
-      const uint32_t old = __hip_atomic_fetch_add(flags + parent, 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (old == 0) break;
-      float sb[6];
-      int sh;
-      load_child(nodes + parent, side ^ 1, sb, sh);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        b[a] = fminf(b[a], sb[a]);
-        b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
-      }
-      h = (h > sh ? h : sh) + 1;
-      if (parent == 0) {
-        hdr->height = h;
-        break;
-      }
-      pp = up;
-      parent = pp >> 1;
-      side = pp & 1;
-      store_child(nodes + parent, side, b, h);
-      if (step + 1 == kRefitMaxSteps) atomicOr(&hdr->bad, 4);
-    }
-  }
-}
 
 // ------------------------------------------------- agglomerative build
 // Hierarchy and refit in one bottom-up pass (Apetrei 2014, the single-pass
@@ -652,12 +433,6 @@ size_t agglo_frontier_cap(int64_t n) {
   return (size_t)(2 * ((n + kRefitChunk - 1) / kRefitChunk) + 64);  // per list (two lists)
 }
 
-// frontier entries: a crossing node has at most two, and every crossing node
-// lies on the root path of some chunk boundary
-size_t refit_frontier_cap(int64_t n) {
-  const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
-  return 2 * (size_t)(2 * 128 * chunks + 64);  // two lists: chunk and super-chunk crossings
-}
 
 // ------------------------------------------------------------ Q16 nodes
 // The 16-bit code of a box's lower (upper) face: the largest (smallest) q
@@ -750,6 +525,412 @@ __global__ __launch_bounds__(kBuildBlock) void k_quantise(const NodeF32 *__restr
   dst[slot] = out;
 }
 
+// ------------------------------------------------------------ bottom-up refit
+// Internal boxes from the leaves up (section 2.1).  One thread per leaf
+// climbs from its leaf; at each parent the first arrival leaves its child
+// record (exact box, reference, height) and stops, the second takes both and
+// climbs on with their union.  Nodes are written whole in their final form:
+// FP32, or Q16 -- outward-rounded child boxes, a point leaf's slot holding
+// the float32 point -- at the depth-first slot with renumbered references.
+// The rounding needs the exact child boxes, so it happens here rather than in
+// a pass over a staged FP32 tree, but not inside the climb itself: a
+// wavefront pays for every instruction any of its lanes runs, and the climbs
+// are divergent, so finished nodes are emitted afterwards by a pass with one
+// thread per node.
+//
+// Phase 1 (k_fit_chunk): a workgroup owns kFitChunk consecutive leaves, two
+// per thread (the LDS records of 2048 leaves fill one CU's 160 KB; larger
+// chunks leave fewer nodes to the slower later phases).  A
+// Karras node's leaf range contains its own index, so a node whose range lies
+// inside the chunk is numbered inside it: the workgroup loads those nodes'
+// parent words and output slots into LDS, the climb inside the chunk reads
+// nothing else from global memory, and child records meet in LDS, the
+// arrivals counted by an LDS atomic at workgroup scope whose value carries
+// the first arrival's height.  After a barrier each thread emits its nodes of
+// the chunk whose two children arrived.  A climb reaching a node whose range
+// leaves the chunk stores its record in the node's staging slot (the FP32
+// node layout; for FP32 trees the node itself) and lists (node, side): in its
+// group's list when the range stays inside the group of kFitGroup chunks,
+// else in the top list.
+// Phase 2 (k_fit_climb, one workgroup per group) climbs from the group's list
+// through nodes inside the group; every arrival at such a node comes from this
+// workgroup, so counters in global memory at workgroup scope order the
+// hand-offs.  Phase 3 (one workgroup) climbs the top list to the root.  The
+// staged records of a node both of whose children have arrived form the FP32
+// node; for Q16 trees such nodes are listed and k_fit_emit quantises them.
+// Each phase starts after a kernel boundary has made the previous one's stores
+// visible; no step needs agent-scope fences (which write back and invalidate
+// the XCDs' L2s).
+constexpr int kFitThreads = 1024;
+constexpr int kFitPerThread = 2;        // leaves (and nodes) per thread
+constexpr int kFitChunk = kFitThreads * kFitPerThread;
+constexpr int kFitWaves = 4;            // per SIMD: one workgroup per CU (LDS)
+constexpr int kFitGroup = 64;           // chunks per group of phase 2
+constexpr int64_t kFitGroupLeaves = (int64_t)kFitChunk * kFitGroup;
+// Bound on the nodes of any root path: the augmented codes' common-prefix
+// lengths grow strictly along a path and are below 63 + 32.
+constexpr int kFitMaxPath = 96;
+// A node whose range crosses an inner chunk boundary of a group holds the two
+// leaves beside that boundary, so it lies on their common ancestors' path:
+// at most (kFitGroup - 1) * kFitMaxPath nodes, two entries each.
+constexpr uint32_t kFitGroupCap = 2 * (kFitGroup - 1) * kFitMaxPath;
+constexpr int kFitMaxSteps = 256;       // > any tree height; only bounds the loops
+constexpr uint32_t kFitDone = 1u << 31;  // LDS counter: both children arrived
+
+int64_t fit_groups(int64_t n) { return (n + kFitGroupLeaves - 1) / kFitGroupLeaves; }
+
+// the top list: nodes crossing a group boundary, likewise
+uint32_t fit_top_cap(int64_t n) { return (uint32_t)(2 * kFitMaxPath * fit_groups(n) + 64); }
+
+// every node finished by phases 2 and 3 was listed by phase 1 or 2 first
+uint32_t fit_emit_cap(int64_t n) {
+  return fit_top_cap(n) + (uint32_t)fit_groups(n) * kFitGroupCap;
+}
+
+// counters (top list, one per group, emit list), the top list, the group
+// lists, the emit list
+size_t fit_lists_bytes(int64_t n) {
+  const size_t g = (size_t)fit_groups(n);
+  return align_up((2 + g) * 4, 256) + align_up((size_t)fit_top_cap(n) * 4, 256) +
+         align_up(g * kFitGroupCap * 4, 256) + (size_t)fit_emit_cap(n) * 4;
+}
+
+struct FitLists {
+  uint32_t *count;  // [0]: top list, [1 + g]: group g, [1 + groups]: emit list
+  int32_t *top;
+  int32_t *group;   // kFitGroupCap entries per group
+  int32_t *emit;
+  uint32_t *emit_count;
+  uint32_t top_cap, emit_cap;
+};
+
+FitLists fit_lists(void *mem, int64_t n) {
+  const size_t g = (size_t)fit_groups(n);
+  char *p = static_cast<char *>(mem);
+  FitLists L;
+  L.count = reinterpret_cast<uint32_t *>(p);
+  L.emit_count = L.count + 1 + g;
+  p += align_up((2 + g) * 4, 256);
+  L.top = reinterpret_cast<int32_t *>(p);
+  L.top_cap = fit_top_cap(n);
+  p += align_up((size_t)L.top_cap * 4, 256);
+  L.group = reinterpret_cast<int32_t *>(p);
+  p += align_up(g * kFitGroupCap * 4, 256);
+  L.emit = reinterpret_cast<int32_t *>(p);
+  L.emit_cap = fit_emit_cap(n);
+  return L;
+}
+
+// child record in the staging node (the FP32 node layout: box at floats
+// 6 * side, reference at word 12 + side, height at 14 + side)
+__device__ __forceinline__ void put_rec(NodeF32 *node, int side, const float b[6], int32_t ref,
+                                        int h) {
+  store_child(node, side, b, h);
+  reinterpret_cast<int32_t *>(node)[12 + side] = ref;
+}
+
+__device__ __forceinline__ void get_rec(const NodeF32 *node, int side, float b[6], int32_t &ref,
+                                        int &h) {
+  load_child(node, side, b, h);
+  ref = reinterpret_cast<const int32_t *>(node)[12 + side];
+}
+
+struct QGrid {
+  float o[3], s[3], inv[3];
+};
+
+__device__ __forceinline__ QGrid load_grid(const TreeHeader *hdr) {
+  QGrid g;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    g.o[a] = hdr->q_origin[a];
+    g.s[a] = hdr->q_scale[a];
+    g.inv[a] = g.s[a] != 0.0f ? 1.0f / g.s[a] : 0.0f;
+  }
+  return g;
+}
+
+// the three Q16 words of one child slot (a point leaf keeps its float32 point)
+template <int KIND>
+__device__ __forceinline__ void q16_slot(const float b[6], int32_t ref, const QGrid &g,
+                                         uint32_t w[3]) {
+  if (KIND == ABX_PRIM_POINTS && ref < 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w[a] = __float_as_uint(b[a]);
+    return;
+  }
+  uint32_t q[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q[a] = q_lo(b[a], g.o[a], g.s[a], g.inv[a]);
+    q[3 + a] = q_hi(b[3 + a], g.o[a], g.s[a], g.inv[a]);
+  }
+#pragma unroll
+  for (int h = 0; h < 3; ++h) w[h] = q[2 * h] | (q[2 * h + 1] << 16);
+}
+
+// a finished node, children in side order, written whole at its slot
+template <int KIND, bool kQ16>
+__device__ __forceinline__ void put_node(void *out, int32_t slot, const float *b0, const float *b1,
+                                         int32_t r0, int32_t r1, int h0, int h1, const QGrid &g) {
+  if (kQ16) {
+    uint32_t w0[3], w1[3];
+    q16_slot<KIND>(b0, r0, g, w0);
+    q16_slot<KIND>(b1, r1, g, w1);
+    NodeQ16 *o = static_cast<NodeQ16 *>(out) + slot;
+    o->a = make_uint4(w0[0], w0[1], w0[2], w1[0]);
+    o->b = make_uint4(w1[1], w1[2], (uint32_t)r0, (uint32_t)r1);
+  } else {
+    float4 *o = reinterpret_cast<float4 *>(static_cast<NodeF32 *>(out) + slot);
+    o[0] = make_float4(b0[0], b0[1], b0[2], b0[3]);
+    o[1] = make_float4(b0[4], b0[5], b1[0], b1[1]);
+    o[2] = make_float4(b1[2], b1[3], b1[4], b1[5]);
+    o[3] = make_float4(__int_as_float(r0), __int_as_float(r1), __int_as_float(h0),
+                       __int_as_float(h1));
+  }
+}
+
+__device__ __forceinline__ void unite(float b[6], const float sb[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    b[a] = fminf(b[a], sb[a]);
+    b[3 + a] = fmaxf(b[3 + a], sb[3 + a]);
+  }
+}
+
+__device__ __forceinline__ void fit_push(const FitLists &L, int64_t f, int64_t l, int32_t pp,
+                                         TreeHeader *hdr) {
+  const int64_t g = f / kFitGroupLeaves;
+  if (l < (g + 1) * kFitGroupLeaves) {
+    const uint32_t e = atomicAdd(L.count + 1 + g, 1u);
+    if (e < kFitGroupCap) L.group[g * kFitGroupCap + e] = pp;
+    else atomicOr(&hdr->bad, 4);
+  } else {
+    const uint32_t e = atomicAdd(L.count, 1u);
+    if (e < L.top_cap) L.top[e] = pp;
+    else atomicOr(&hdr->bad, 4);
+  }
+}
+
+// output slot of node x: its depth-first index when renumbering, else x
+__device__ __forceinline__ int32_t fit_slot(const int32_t *__restrict__ pre, int64_t x, int64_t ni,
+                                            TreeHeader *hdr) {
+  if (!pre) return (int32_t)x;
+  const int32_t s = pre[x];
+  if (s < 0 || s >= ni) {
+    atomicOr(&hdr->bad, 8);
+    return -1;
+  }
+  return s;
+}
+
+// Phase 1.  The climbs only move records (cheap, but divergent: a wavefront
+// keeps looping for its longest climb); the nodes they finish are written
+// after a barrier, one thread per node.
+template <int KIND, bool kQ16>
+__global__ __launch_bounds__(kFitThreads) __attribute__((amdgpu_waves_per_eu(kFitWaves))) void k_fit_chunk(
+    const float *__restrict__ prims, const int32_t *__restrict__ perm, int64_t n,
+    const uint64_t *__restrict__ pw_leaf, const uint64_t *__restrict__ pw_int,
+    const int32_t *__restrict__ pre, void *out, NodeF32 *stage, TreeHeader *hdr, void *box_rec,
+    FitLists lists) {
+  // after a failed sort the permutation and hierarchy are not valid (the
+  // whole workgroup leaves: no barrier is skipped by part of it)
+  if (hdr->bad & kBadSort) return;
+  __shared__ uint64_t s_pw[kFitChunk];
+  __shared__ int32_t s_slot[kFitChunk];
+  __shared__ uint32_t s_cnt[kFitChunk];
+  __shared__ int32_t s_ref[2 * kFitChunk];
+  __shared__ float s_box[2 * kFitChunk * 6];
+  // node and leaf indices fit in 31 bits (the parent words hold them)
+  const int32_t c0 = (int32_t)blockIdx.x * kFitChunk, ni = (int32_t)(n - 1);
+  // leaf and node r * kFitThreads + threadIdx.x of the chunk, for each r
+  float b[kFitPerThread][6];
+  int32_t ref[kFitPerThread];
+  uint64_t pw[kFitPerThread];
+#pragma unroll
+  for (int r = 0; r < kFitPerThread; ++r) {
+    const int t = r * kFitThreads + (int)threadIdx.x;
+    const int32_t x = c0 + t;
+    if (x < ni) {
+      s_pw[t] = pw_int[x];
+      s_slot[t] = fit_slot(pre, x, ni, hdr);
+    }
+    s_cnt[t] = 0;
+    ref[r] = 0;
+    pw[r] = 0;
+    if (x < n) {
+      const int32_t orig = perm[x];
+      if (n > 1) pw[r] = pw_leaf[x];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[r][a] = KIND == ABX_PRIM_POINTS ? prims[3 * (int64_t)orig + a] : prims[6 * (int64_t)orig + a];
+        b[r][3 + a] = KIND == ABX_PRIM_POINTS ? b[r][a] : prims[6 * (int64_t)orig + 3 + a];
+      }
+      if (KIND == ABX_PRIM_BOXES && box_rec) {
+        // exact box record of a Q16 box tree, addressed by primitive index
+        float4 *o = static_cast<float4 *>(box_rec) + 2 * (int64_t)orig;
+        o[0] = make_float4(b[r][0], b[r][1], b[r][2], b[r][3]);
+        o[1] = make_float4(b[r][4], b[r][5], __int_as_float(x), 0.0f);
+      }
+      ref[r] = ~orig;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kFitPerThread; ++r) {
+    const int32_t x = c0 + r * kFitThreads + (int)threadIdx.x;
+    if (x >= n || n == 1) break;
+    float *bb = b[r];
+    int32_t rf = ref[r];
+    uint64_t w = pw[r];
+    int h = 0;
+    for (int step = 0; step < kFitMaxSteps; ++step) {
+      const int32_t pp = (int32_t)(uint32_t)w;
+      const int32_t parent = pp >> 1, j = (int32_t)(uint32_t)(w >> 32);
+      const int side = pp & 1;
+      const int u = parent - c0;
+      // the parent's range [min(parent, j), max(parent, j)] inside the chunk
+      if ((uint32_t)u >= (uint32_t)kFitChunk || (uint32_t)(j - c0) >= (uint32_t)kFitChunk) {
+        put_rec(stage + parent, side, bb, rf, h);
+        fit_push(lists, parent < j ? parent : j, parent < j ? j : parent, pp, hdr);
+        break;
+      }
+      const int mine = 2 * u + side, other = mine ^ 1;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) s_box[6 * mine + a] = bb[a];
+      s_ref[mine] = rf;
+      // the first arrival leaves height + 1 (never 0); the second reads it
+      // back, then leaves both heights and the done mark for the emit below
+      const uint32_t old = __hip_atomic_fetch_max(&s_cnt[u], (uint32_t)h + 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      const uint32_t sh = old - 1u;
+      s_cnt[u] = kFitDone | (side == 0 ? (uint32_t)h << 8 | sh : sh << 8 | (uint32_t)h);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bb[a] = fminf(bb[a], s_box[6 * other + a]);
+        bb[3 + a] = fmaxf(bb[3 + a], s_box[6 * other + 3 + a]);
+      }
+      h = (h > (int)sh ? h : (int)sh) + 1;
+      rf = s_slot[u];
+      w = s_pw[u];
+      if (parent == 0) {
+        hdr->height = h;
+        break;
+      }
+      if (step + 1 == kFitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+  __syncthreads();
+  // emit: this thread's nodes that were finished inside the chunk
+  QGrid g{};
+  if (kQ16) g = load_grid(hdr);
+#pragma unroll
+  for (int r = 0; r < kFitPerThread; ++r) {
+    const int t = r * kFitThreads + (int)threadIdx.x;
+    if (c0 + t >= ni) break;
+    const uint32_t c = s_cnt[t];
+    const int32_t slot = s_slot[t];
+    if ((c & kFitDone) && slot >= 0) {
+      float b0[6], b1[6];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        b0[a] = s_box[12 * t + a];
+        b1[a] = s_box[12 * t + 6 + a];
+      }
+      put_node<KIND, kQ16>(out, slot, b0, b1, s_ref[2 * t], s_ref[2 * t + 1], (int)((c >> 8) & 0xff),
+                           (int)(c & 0xff), g);
+    }
+  }
+}
+
+// Phases 2 and 3: climbs from listed (node, side) entries whose records are
+// staged, counting arrivals in the global flags (cleared by the hierarchy
+// kernel).  kGroup: stop at nodes leaving group blockIdx.x and list them for
+// the top pass.
+template <bool kQ16, bool kGroup>
+__global__ __launch_bounds__(kFitThreads) void k_fit_climb(
+    int64_t n, const uint64_t *__restrict__ pw_int, const int32_t *__restrict__ pre,
+    NodeF32 *stage, uint32_t *flags, TreeHeader *hdr, FitLists lists) {
+  const int64_t ni = n - 1;
+  const int64_t g0 = kGroup ? (int64_t)blockIdx.x * kFitGroupLeaves : 0;
+  const int64_t g1 = g0 + kFitGroupLeaves;
+  const int32_t *list = kGroup ? lists.group + (int64_t)blockIdx.x * kFitGroupCap : lists.top;
+  const uint32_t cnt =
+      min(lists.count[kGroup ? 1 + blockIdx.x : 0], kGroup ? kFitGroupCap : lists.top_cap);
+  for (uint32_t e = threadIdx.x; e < cnt; e += kFitThreads) {
+    int32_t pp = list[e];
+    int64_t parent = pp >> 1;
+    int side = pp & 1;
+    float b[6];
+    int32_t ref;
+    int h;
+    get_rec(stage + parent, side, b, ref, h);
+    for (int step = 0; step < kFitMaxSteps; ++step) {
+      // read-only: fetched ahead of the hand-off
+      const uint64_t up = parent != 0 ? pw_int[parent] : 0;
+      const int32_t slot = fit_slot(pre, parent, ni, hdr);
+      const uint32_t old = __hip_atomic_fetch_add(flags + parent, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      // both records staged: the FP32 node is complete, a Q16 one is listed
+      if (kQ16) {
+        const uint32_t e2 = atomicAdd(lists.emit_count, 1u);
+        if (e2 < lists.emit_cap) lists.emit[e2] = (int32_t)parent;
+        else atomicOr(&hdr->bad, 4);
+      }
+      float sb[6];
+      int32_t sref;
+      int sh;
+      get_rec(stage + parent, side ^ 1, sb, sref, sh);
+      unite(b, sb);
+      h = (h > sh ? h : sh) + 1;
+      ref = slot;
+      if (parent == 0) {
+        hdr->height = h;
+        break;
+      }
+      pp = (int32_t)(uint32_t)up;
+      parent = pp >> 1;
+      side = pp & 1;
+      put_rec(stage + parent, side, b, ref, h);
+      if (kGroup) {
+        const int64_t j = (int64_t)(uint32_t)(up >> 32);
+        const int64_t f = parent < j ? parent : j, l = parent < j ? j : parent;
+        if (f < g0 || l >= g1) {
+          const uint32_t e2 = atomicAdd(lists.count, 1u);
+          if (e2 < lists.top_cap) lists.top[e2] = pp;
+          else atomicOr(&hdr->bad, 4);
+          break;
+        }
+      }
+      if (step + 1 == kFitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+}
+
+// Q16 nodes finished by phases 2 and 3, quantised from their staged records
+// (one thread per listed node)
+template <int KIND>
+__global__ __launch_bounds__(kBuildBlock) void k_fit_emit(int64_t n, const int32_t *__restrict__ pre,
+                                                          const NodeF32 *__restrict__ stage,
+                                                          void *out, TreeHeader *hdr,
+                                                          FitLists lists) {
+  const uint32_t cnt = min(*lists.emit_count, lists.emit_cap);
+  const QGrid g = load_grid(hdr);
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+    const int64_t x = lists.emit[e];
+    const int32_t slot = fit_slot(pre, x, n - 1, hdr);
+    if (slot < 0) continue;
+    float b0[6], b1[6];
+    int32_t r0, r1;
+    int h0, h1;
+    get_rec(stage + x, 0, b0, r0, h0);
+    get_rec(stage + x, 1, b1, r1, h1);
+    put_node<KIND, true>(out, slot, b0, b1, r0, r1, h0, h1, g);
+  }
+}
+
 // ------------------------------------------------------ depth-first order
 // Nodes of a Karras tree renumbered in depth-first (pre-)order, left child
 // first: the root is 0 and a node's left child follows it, so a walk going
@@ -768,11 +949,11 @@ constexpr int kPreRounds = 7;
 // both stay below 128, so neither carries into the other) -- and the
 // ancestor to add next (low half, -1 when the root has been passed), so a
 // round gathers one word per node
-__global__ __launch_bounds__(kBuildBlock) void k_pre_init(const int32_t *__restrict__ parent_int,
+__global__ __launch_bounds__(kBuildBlock) void k_pre_init(const uint64_t *__restrict__ pw_int,
                                                           int64_t ni, uint64_t *__restrict__ w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ni) return;
-  const int32_t pp = i == 0 ? -1 : parent_int[i];
+  const int32_t pp = i == 0 ? -1 : (int32_t)(uint32_t)pw_int[i];
   const uint32_t left = pp >= 0 && (pp & 1) == 0 ? 1u : 0u;  // a left child
   const uint32_t val = pp >= 0 ? left | (1u << 16) : 0u;
   const int32_t anc = pp >= 0 ? pp >> 1 : -1;
@@ -817,12 +998,12 @@ __global__ __launch_bounds__(kBuildBlock) void k_pre_last(const uint64_t *__rest
 }
 
 // scratch: 2 * ni words + ni int32 for the result (and ni for the depths)
-abx_status launch_preorder(const int32_t *parent_int, const int32_t *other_end, int64_t ni,
+abx_status launch_preorder(const uint64_t *pw_int, const int32_t *other_end, int64_t ni,
                            uint64_t *work, int32_t *pre, int32_t *depth, hipStream_t s) {
   if (ni <= 0) return ABX_OK;
   const unsigned g = grid_for(ni, kBuildBlock);
   uint64_t *buf[2] = {work, work + ni};
-  ABX_TRY(launch("preorder", s, [&] { k_pre_init<<<g, kBuildBlock, 0, s>>>(parent_int, ni, buf[0]); }));
+  ABX_TRY(launch("preorder", s, [&] { k_pre_init<<<g, kBuildBlock, 0, s>>>(pw_int, ni, buf[0]); }));
   for (int r = 0; r + 1 < kPreRounds; ++r) {
     const int a = r & 1, b = a ^ 1;
     ABX_TRY(launch("preorder", s, [&] { k_pre_jump<<<g, kBuildBlock, 0, s>>>(buf[a], ni, buf[b]); }));
@@ -1021,56 +1202,73 @@ abx_status launch_morton(int kind, const float *prims, int64_t n, const float *s
   });
 }
 
-abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
-                         int32_t *parent_leaf, int32_t *parent_int, int32_t *other_end,
-                         uint32_t *flags, const TreeHeader *hdr, hipStream_t s) {
+abx_status launch_karras(bool wide, const void *keys, int64_t n, uint64_t *pw_leaf, uint64_t *pw_int,
+                         int32_t *other_end, uint32_t *flags, const TreeHeader *hdr, hipStream_t s) {
   if (n < 2) return ABX_OK;
   const unsigned g = grid_for(n - 1, kBuildBlock);
   if (wide)
     return launch("karras", s, [&] {
-      k_karras<uint64_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint64_t *>(keys), n, nodes,
-                                                   parent_leaf, parent_int, other_end, flags, hdr);
+      k_karras<uint64_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint64_t *>(keys), n, pw_leaf,
+                                                   pw_int, other_end, flags, hdr);
     });
   return launch("karras", s, [&] {
-    k_karras<uint32_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint32_t *>(keys), n, nodes,
-                                                 parent_leaf, parent_int, other_end, flags, hdr);
+    k_karras<uint32_t><<<g, kBuildBlock, 0, s>>>(static_cast<const uint32_t *>(keys), n, pw_leaf,
+                                                 pw_int, other_end, flags, hdr);
   });
 }
 
+// lists of the refit (and of the agglomerative build, which shares the region)
+size_t refit_lists_bytes(int64_t n) {
+  const size_t agglo = 256 + 2 * agglo_frontier_cap(n) * 4;
+  const size_t fit = fit_lists_bytes(n);
+  return fit > agglo ? fit : agglo;
+}
+
 abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
-                        const int32_t *parent_leaf, const int32_t *parent_int,
-                        const int32_t *other_end, NodeF32 *nodes, uint32_t *flags,
-                        TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
-                        uint32_t *frontier_count, hipStream_t s) {
+                        const uint64_t *pw_leaf, const uint64_t *pw_int, const int32_t *pre,
+                        void *out, NodeF32 *stage, uint32_t *flags, TreeHeader *hdr, void *box_rec,
+                        void *lists_mem, hipStream_t s) {
   if (n == 0) return ABX_OK;
-  const unsigned g = grid_for(n, kRefitChunk);
-  const uint32_t cap = (uint32_t)(refit_frontier_cap(n) / 2);  // per list
-  ABX_TRY(fill_u32(frontier_count, 0, 2, s));
-#define ABX_REFIT(KD, QQ)                                                                        \
-  ABX_TRY(launch("refit", s, [&] {                                                              \
-    k_refit_local<KD, QQ><<<g, kRefitThreads, 0, s>>>(prims, perm, n, parent_leaf, parent_int, \
-                                                       other_end, nodes, hdr, q16_leaves,       \
-                                                       frontier, frontier_count, cap);          \
+  const FitLists L = fit_lists(lists_mem, n);
+  const int64_t groups = fit_groups(n);
+  ABX_TRY(fill_u32(L.count, 0, (size_t)(2 + groups), s));
+  const unsigned g = grid_for(n, kFitChunk);
+#define ABX_FIT(KD, QQ)                                                                        \
+  ABX_TRY(launch("refit", s, [&] {                                                             \
+    k_fit_chunk<KD, QQ><<<g, kFitThreads, 0, s>>>(prims, perm, n, pw_leaf, pw_int, pre, out,   \
+                                                  stage, hdr, box_rec, L);                     \
   }))
   if (kind == ABX_PRIM_POINTS) {
-    if (q16) ABX_REFIT(ABX_PRIM_POINTS, true);
-    else ABX_REFIT(ABX_PRIM_POINTS, false);
+    if (q16) ABX_FIT(ABX_PRIM_POINTS, true);
+    else ABX_FIT(ABX_PRIM_POINTS, false);
   } else {
-    if (q16) ABX_REFIT(ABX_PRIM_BOXES, true);
-    else ABX_REFIT(ABX_PRIM_BOXES, false);
+    if (q16) ABX_FIT(ABX_PRIM_BOXES, true);
+    else ABX_FIT(ABX_PRIM_BOXES, false);
   }
-#undef ABX_REFIT
-  if (n <= kRefitChunk) return ABX_OK;
-  int32_t *frontier2 = frontier + cap;
-  const unsigned g2 = (unsigned)((n + kMidLeaves - 1) / kMidLeaves);
+#undef ABX_FIT
+  if (n <= kFitChunk) return ABX_OK;
   ABX_TRY(launch("refit_mid", s, [&] {
-    k_refit_mid<<<g2, kRefitThreads, 0, s>>>(parent_int, other_end, nodes, flags, hdr, frontier,
-                                             frontier_count, frontier2, frontier_count + 1, cap);
+    if (q16)
+      k_fit_climb<true, true><<<(unsigned)groups, kFitThreads, 0, s>>>(n, pw_int, pre, stage, flags,
+                                                                       hdr, L);
+    else
+      k_fit_climb<false, true><<<(unsigned)groups, kFitThreads, 0, s>>>(n, pw_int, pre, stage,
+                                                                        flags, hdr, L);
   }));
-  if (n <= kMidLeaves) return ABX_OK;
-  return launch("refit_top", s, [&] {
-    k_refit_top<<<1, kRefitThreads, 0, s>>>(parent_int, nodes, flags, hdr, frontier2,
-                                            frontier_count + 1, cap);
+  if (n > kFitGroupLeaves)
+    ABX_TRY(launch("refit_top", s, [&] {
+      if (q16)
+        k_fit_climb<true, false><<<1, kFitThreads, 0, s>>>(n, pw_int, pre, stage, flags, hdr, L);
+      else
+        k_fit_climb<false, false><<<1, kFitThreads, 0, s>>>(n, pw_int, pre, stage, flags, hdr, L);
+    }));
+  if (!q16) return ABX_OK;
+  const unsigned ge = (unsigned)std::min<int64_t>(grid_for(L.emit_cap, kBuildBlock), 1024);
+  return launch("refit_emit", s, [&] {
+    if (kind == ABX_PRIM_POINTS)
+      k_fit_emit<ABX_PRIM_POINTS><<<ge, kBuildBlock, 0, s>>>(n, pre, stage, out, hdr, L);
+    else
+      k_fit_emit<ABX_PRIM_BOXES><<<ge, kBuildBlock, 0, s>>>(n, pre, stage, out, hdr, L);
   });
 }
 

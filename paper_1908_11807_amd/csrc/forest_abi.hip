@@ -34,17 +34,13 @@ abx_status forest_launch_nearest_stats(const TreeArgs &t, int format, const int6
                                        const int32_t *order, int k, int32_t *stats, hipStream_t s);
 int forest_max_trees();
 // build.hip
-abx_status launch_karras(bool wide, const void *keys, int64_t n, NodeF32 *nodes,
-                         int32_t *parent_leaf, int32_t *parent_int, int32_t *other_end,
-                         uint32_t *flags, const TreeHeader *hdr, hipStream_t s);
+abx_status launch_karras(bool wide, const void *keys, int64_t n, uint64_t *pw_leaf, uint64_t *pw_int,
+                         int32_t *other_end, uint32_t *flags, const TreeHeader *hdr, hipStream_t s);
 abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *perm, int64_t n,
-                        const int32_t *parent_leaf, const int32_t *parent_int,
-                        const int32_t *other_end, NodeF32 *nodes, uint32_t *flags,
-                        TreeHeader *hdr, void *q16_leaves, int32_t *frontier,
-                        uint32_t *frontier_count, hipStream_t s);
-abx_status launch_quantise(int kind, const NodeF32 *src, int64_t ni, TreeHeader *hdr,
-                           const int32_t *pre, NodeQ16 *dst, hipStream_t s);
-size_t refit_frontier_cap(int64_t n);
+                        const uint64_t *pw_leaf, const uint64_t *pw_int, const int32_t *pre,
+                        void *out, NodeF32 *stage, uint32_t *flags, TreeHeader *hdr, void *box_rec,
+                        void *lists_mem, hipStream_t s);
+size_t refit_lists_bytes(int64_t n);
 int max_tree_depth();
 
 namespace {
@@ -91,16 +87,16 @@ ForestLayout forest_layout(int T, int64_t N, bool q16) {
   off = align_up(off + n * 8, 256);
   L.sorted = off;
   off = align_up(off + n * 8, 256);
-  L.parent_leaf = off;
-  off = align_up(off + n * 4, 256);
+  L.parent_leaf = off;  // parent words
+  off = align_up(off + n * 8, 256);
   L.parent_int = off;
-  off = align_up(off + n * 4, 256);
+  off = align_up(off + n * 8, 256);
   L.other_end = off;
   off = align_up(off + n * 4, 256);
   L.flags = off;
   off = align_up(off + n * 4, 256);
   L.frontier = off;
-  off = align_up(off + 256 + refit_frontier_cap(N) * 4, 256);
+  off = align_up(off + refit_lists_bytes(N), 256);
   L.staging = off;
   off = align_up(off + (q16 ? (size_t)L.ni * sizeof(NodeF32) : 0), 256);
   L.sort = off;
@@ -247,20 +243,16 @@ abx_status abx_forest_build(const abx_forest_primitives *prims, void *tree_mem, 
     int32_t *perm = reinterpret_cast<int32_t *>(tree + L.leaves);
     NodeF32 *fnodes = q16 ? reinterpret_cast<NodeF32 *>(sc + L.staging)
                           : reinterpret_cast<NodeF32 *>(tree + L.nodes);
-    int32_t *parent_leaf = reinterpret_cast<int32_t *>(sc + L.parent_leaf);
-    int32_t *parent_int = reinterpret_cast<int32_t *>(sc + L.parent_int);
+    uint64_t *pw_leaf = reinterpret_cast<uint64_t *>(sc + L.parent_leaf);
+    uint64_t *pw_int = reinterpret_cast<uint64_t *>(sc + L.parent_int);
     uint32_t *flags = reinterpret_cast<uint32_t *>(sc + L.flags);
     ABX_TRY(radix_sort(sc + L.keys, nullptr, N, kForestKeyBits, sc + L.sorted, perm, sc + L.sort,
                        radix_sort_scratch_bytes(N, kForestKeyBits), s,
                        reinterpret_cast<uint32_t *>(&hdr->bad), kBadSort));
-    ABX_TRY(launch_karras(true, sc + L.sorted, N, fnodes, parent_leaf, parent_int, other_end, flags, hdr, s));
-    ABX_TRY(launch_refit(ABX_PRIM_POINTS, q16, prims->data, perm, N, parent_leaf, parent_int, other_end,
-                         fnodes, flags, hdr, tree + L.leaves,
-                         reinterpret_cast<int32_t *>(sc + L.frontier + 256),
-                         reinterpret_cast<uint32_t *>(sc + L.frontier), s));
-    if (q16)
-      ABX_TRY(launch_quantise(ABX_PRIM_POINTS, fnodes, L.ni, hdr, nullptr,
-                              reinterpret_cast<NodeQ16 *>(tree + L.nodes), s));
+    ABX_TRY(launch_karras(true, sc + L.sorted, N, pw_leaf, pw_int, other_end, flags, hdr, s));
+    // nodes written whole by the refit (Q16 directly, build order)
+    ABX_TRY(launch_refit(ABX_PRIM_POINTS, q16, prims->data, perm, N, pw_leaf, pw_int, nullptr,
+                         tree + L.nodes, fnodes, flags, hdr, nullptr, sc + L.frontier, s));
   }
   ABX_TRY(forest_launch_roots(offs, T, other_end, reinterpret_cast<const int32_t *>(tree + L.leaves),
                               roots, s));

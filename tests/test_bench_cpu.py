@@ -35,10 +35,11 @@ def test_build_bytes_differences():
     fp32 = bench.build_bytes_per_prim("fp32", 21)
     q16 = bench.build_bytes_per_prim("q16", 21)
     q16_df = bench.build_bytes_per_prim("q16", 21, depth_first=True)
-    # quantisation reads a 64-byte node and writes a 32-byte one
-    assert q16 - fp32 == 64 + 32
-    # the depth-first renumbering is charged only when it ran
-    assert q16_df > q16
+    # the refit writes each node once in its final format: 32 bytes, not 64
+    assert fp32 - q16 == 64 - 32
+    # the depth-first renumbering is charged only when it ran: the pointer
+    # jumping (init 16, 6 rounds of 24, last round 24) and the refit's slot read
+    assert q16_df - q16 == 16 + 6 * 24 + 24 + 4
     # 30-bit keys: half the key bytes and half the sort passes
     assert bench.build_bytes_per_prim("fp32", 10) < fp32
     # box primitives read 24 bytes where points read 12, three times (scene,

@@ -95,6 +95,15 @@ def _check_tree_vs_oracle(orc, prims, kind, bits, fmt, node_order="auto"):
                 q = ck[:, s] == 1 if kind == 0 else np.ones(ni, bool)   # quantised slots
                 assert np.all(d[q, :3] <= child_box[q, s, :3]), "q16 lower corner not outward"
                 assert np.all(d[q, 3:] >= child_box[q, s, 3:]), "q16 upper corner not outward"
+                # and the tightest such codes: one step inward leaves the box
+                code = got[key].astype(np.int64)
+                up = dequantise(np.minimum(code + 1, 65535), list(lay.q16_origin), list(lay.q16_scale))
+                down = dequantise(np.maximum(code - 1, 0), list(lay.q16_origin), list(lay.q16_scale))
+                flat = np.asarray(list(lay.q16_scale), np.float32) == 0   # one code per axis
+                lo_ok = flat | (code[:, :3] == 65535) | (up[:, :3] > child_box[:, s, :3])
+                hi_ok = flat | (code[:, 3:] == 0) | (down[:, 3:] < child_box[:, s, 3:])
+                assert np.all(lo_ok[q]), "q16 lower corner not the tightest code"
+                assert np.all(hi_ok[q]), "q16 upper corner not the tightest code"
     if fmt == "q16":
         sp = np.asarray(prims, np.float32).reshape(n, -1)[ref["perm"]]
         leafbox = np.concatenate([sp[:, :3], sp[:, :3]], axis=1) if kind == 0 else sp
@@ -124,7 +133,7 @@ def test_build_depth_first_small(orc, n):
 
 @pytest.mark.parametrize("kind,fmt,order", [(0, "fp32", "auto"), (1, "q16", "auto"), (0, "q16", "depth_first")])
 def test_build_all_refit_phases(orc, kind, fmt, order):
-    # 1.3e6 leaves: 159 chunks of 8192 in three groups of 64 (the last one
+    # 1.3e6 leaves: 635 chunks of 2048 in 10 groups of 64 (the last one
     # ragged), so the in-chunk, in-group and cross-group refit phases all run
     pts = datagen.shell(1_300_000, 77, 0.99, 1.01)
     prims = pts if kind == 0 else datagen.boxes_around(pts, 78, 0.001)
@@ -132,11 +141,14 @@ def test_build_all_refit_phases(orc, kind, fmt, order):
     assert t.height >= 2
 
 
-@pytest.mark.parametrize("n", [524_287, 524_288, 524_289, 532_481])
-def test_build_group_edges(orc, n):
-    # one group of 64 chunks exactly, one leaf either side, and one leaf past
-    # the first chunk of the second group: the top pass runs only past 524 288
-    _check_tree_vs_oracle(orc, datagen.clusters(n, 90), 0, 21, "fp32")
+@pytest.mark.parametrize("n", [2047, 2048, 2049, 4097, 131_071, 131_072, 131_073, 133_121, 262_145])
+@pytest.mark.parametrize("fmt,order", [("fp32", "auto"), ("q16", "depth_first")])
+def test_build_group_edges(orc, n, fmt, order):
+    # chunks of 2048 leaves in groups of 64: one chunk or group exactly, one
+    # leaf either side, one leaf past the first chunk of the second group, and
+    # one past two groups; the in-group pass runs past 2048 leaves and the
+    # top pass past 131 072
+    _check_tree_vs_oracle(orc, datagen.clusters(n, 90), 0, 21, fmt, order)
 
 
 def test_build_duplicates_and_degenerate_axis(orc):
