@@ -49,7 +49,9 @@ def parse():
     ap.add_argument("--serve-merge", type=int, default=0,
                     help="queries per merged launch (0: the library default, <0: no merging)")
     ap.add_argument("--serve-small", type=int, default=0,
-                    help="largest request that may be merged (0: the library default)")
+                    help="largest small request (0: the library default)")
+    ap.add_argument("--serve-merge-large", type=int, default=0,
+                    help="queries per merged launch of large requests (0: the library default, <0: none)")
     ap.add_argument("--trees", type=int, default=256, help="forest size (C4)")
     ap.add_argument("--paper-sizes", default="1e4,1e5,1e6,1e7",
                     help="m = n sweep of the paper's filled and hollow cases (PAPER)")
@@ -584,7 +586,8 @@ def bench_serving(args, standalone):
     torch.cuda.synchronize()
     budget = 2 << 30
     srv = abx.Server(slots=args.serve_slots, budget_bytes=budget, host_bytes=2 << 30,
-                     merge_queries=args.serve_merge, small_queries=args.serve_small)
+                     merge_queries=args.serve_merge, small_queries=args.serve_small,
+                     merge_large=args.serve_merge_large)
     tids = [srv.add_tree(t) for t in trees]
     kinds = ("radius", 1, 8, 32)
 
@@ -646,7 +649,8 @@ def bench_serving(args, standalone):
                              "device_p99_ms": round(1e3 * float(np.percentile(gpu_t, 99)), 3)})
     st = srv.stats()
     out["server"] = {"slots": args.serve_slots, "merge_queries": args.serve_merge,
-                     "small_queries": args.serve_small, "budget_bytes": budget,
+                     "small_queries": args.serve_small, "merge_large": args.serve_merge_large,
+                     "budget_bytes": budget,
                      "max_in_flight": st["max_in_flight"], "batches": st["batches"],
                      "requests": st["completed"], "device_high_water": st["device_high_water"],
                      "failed": st["failed"]}

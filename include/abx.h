@@ -434,11 +434,12 @@ abx_status abx_graph_destroy(void *graph_exec);
  * tree is built once and queried many times, section 2.2; the batched mode
  * of section 2.2 applied across requests).  A scheduler thread owns `slots`
  * HIP streams.  Queued requests on the same tree with the same predicate
- * (nearest with the same k, or radius with the same r) that are small are
- * MERGED: the first waiting one takes the later ones of its class along, up
- * to merge_queries queries, and they run as one launch sequence over their
- * concatenated queries; each request's rows are copied back to its own
- * results.  Admission serves the queue in order within each size class
+ * (nearest with the same k, or radius with the same r) and of the same size
+ * class are MERGED: the first waiting one takes the later ones of its class
+ * along, up to merge_queries queries for small requests and merge_large for
+ * large ones (which queue beside each other only when the slots are behind),
+ * and they run as one launch sequence over their concatenated queries; each
+ * request's rows are copied back to its own results.  Admission serves the queue in order within each size class
  * (small / large by small_queries): a batch starts as soon as a slot is free
  * and its device reservation fits in the caller's arena (the HBM budget);
  * a request of one class may pass one of the other that cannot start (no
@@ -475,8 +476,11 @@ typedef struct {
   int64_t merge_queries;  /* a merged launch holds at most this many queries
                              (0: 32768; < 0: no merging)                     */
   int64_t small_queries;  /* requests of at most this many queries are
-                             "small": they may be merged, and the two size
-                             classes may pass each other (0: 8192)          */
+                             "small", and the two size classes may pass
+                             each other (0: 8192)                           */
+  int64_t merge_large;    /* large requests of one class queued together are
+                             merged up to this many queries (0: 4 x
+                             merge_queries; < 0: not merged)                */
 } abx_server_config;
 
 typedef struct {

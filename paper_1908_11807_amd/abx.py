@@ -86,7 +86,7 @@ class ServerConfig(C.Structure):
     _fields_ = [("slots", C.c_int32), ("arena", C.c_void_p), ("arena_bytes", C.c_size_t),
                 ("host_bytes", C.c_size_t), ("poll_us", C.c_int32), ("simulate", C.c_int32),
                 ("sim_ns_per_query", C.c_double), ("merge_queries", C.c_int64),
-                ("small_queries", C.c_int64)]
+                ("small_queries", C.c_int64), ("merge_large", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -664,18 +664,20 @@ class Server:
     slots: concurrent batches (one HIP stream each); budget_bytes: the HBM
     arena for in-flight request data (allocated here with PyTorch and handed
     to the library); host_bytes: pinned host result arena (allocated by the
-    library); merge_queries / small_queries: merge limits (0: the library's
-    defaults; merge_queries < 0 turns merging off).  simulate=True runs the
-    scheduler without the GPU.
+    library); merge_queries / small_queries / merge_large: merge limits and
+    size classes (0: the library's defaults; a negative merge limit turns
+    that merging off).  simulate=True runs the scheduler without the GPU.
     """
 
     def __init__(self, slots=4, budget_bytes=1 << 30, host_bytes=1 << 30, simulate=False,
-                 sim_ns_per_query=0.0, poll_us=0, device="cuda", merge_queries=0, small_queries=0):
+                 sim_ns_per_query=0.0, poll_us=0, device="cuda", merge_queries=0, small_queries=0,
+                 merge_large=0):
         L = _lib()
         self.arena = None if simulate else torch.empty(int(budget_bytes), dtype=torch.uint8, device=device)
         cfg = ServerConfig(int(slots), self.arena.data_ptr() if self.arena is not None else None,
                            int(budget_bytes), int(host_bytes), int(poll_us), 1 if simulate else 0,
-                           float(sim_ns_per_query), int(merge_queries), int(small_queries))
+                           float(sim_ns_per_query), int(merge_queries), int(small_queries),
+                           int(merge_large))
         h = C.c_void_p()
         _check(L.abx_server_create(C.byref(cfg), C.byref(h)), "abx_server_create")
         self._h = h

@@ -163,7 +163,8 @@ struct Slot {
 struct abx_server {
   abx_server_config cfg;
   int device = 0;
-  int64_t merge_queries = 0, small_queries = 0;  // resolved merge limits (0: no merging)
+  // resolved merge limits (0: no merging): small batches, large batches
+  int64_t merge_queries = 0, small_queries = 0, merge_large = 0;
   std::vector<const abx_bvh *> trees;
   std::vector<Slot> slots;
   Arena dev, host;
@@ -413,9 +414,12 @@ void complete_batch(abx_server *S, Batch *b) {
   finish_batch(S, b, ABX_OK);
 }
 
-// The batch a request heads: itself, and when it is small, the later queued
-// small requests of its class (in queue order) while the batch stays within
-// the merge limits.  Members leave the queue.
+// The batch a request heads: itself and the later queued requests of its
+// class and size class (in queue order) while the batch stays within the
+// merge limit of that size class.  Members leave the queue.  Large requests
+// find others queued beside them only when the slots are behind, so their
+// merging acts under backlog: one launch sequence over more queries fills
+// the GPU better than several overlapping ones.
 Batch *form_batch(abx_server *S, std::deque<Req *>::iterator head) {
   Req *h = *head;
   Batch *b = new (std::nothrow) Batch;
@@ -429,10 +433,11 @@ Batch *form_batch(abx_server *S, std::deque<Req *>::iterator head) {
   b->reqs.push_back(h);
   b->M = h->r.m;
   auto it = S->queue.erase(head);
-  if (!b->large && S->merge_queries > 0) {
+  const int64_t limit = b->large ? S->merge_large : S->merge_queries;
+  if (limit > 0) {
     while (it != S->queue.end() && (int)b->reqs.size() < kMaxBatchRequests) {
       Req *q = *it;
-      if (!is_large(S, q) && same_class(h, q) && b->M + q->r.m <= S->merge_queries) {
+      if (is_large(S, q) == b->large && same_class(h, q) && b->M + q->r.m <= limit) {
         q->base = b->M;
         b->M += q->r.m;
         b->reqs.push_back(q);
@@ -754,6 +759,7 @@ abx_status abx_server_create(const abx_server_config *cfg, abx_server **out) {
   S->cfg = *cfg;
   S->merge_queries = cfg->merge_queries == 0 ? 32768 : std::max<int64_t>(0, cfg->merge_queries);
   S->small_queries = cfg->small_queries > 0 ? cfg->small_queries : 8192;
+  S->merge_large = cfg->merge_large == 0 ? 4 * S->merge_queries : std::max<int64_t>(0, cfg->merge_large);
   S->dev.reset(cfg->arena_bytes);
   S->host.reset(cfg->host_bytes);
   S->dev_base = static_cast<char *>(cfg->arena);

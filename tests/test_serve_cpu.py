@@ -186,7 +186,7 @@ def test_small_requests_pass_a_blocked_large_one():
     # two slots: at most one large batch runs, so a second large request
     # waits and the small one behind it starts first
     s = _server(slots=2, budget_bytes=1 << 30, host_bytes=1 << 28, sim_ns_per_query=200,
-                merge_queries=0, small_queries=1000)
+                merge_queries=0, small_queries=1000, merge_large=-1)
     big = np.zeros((20_000, 3), np.float32)
     small = np.zeros((10, 3), np.float32)
     t1 = s.submit(0, abx.REQ_NEAREST, big, k=4)
@@ -197,6 +197,27 @@ def test_small_requests_pass_a_blocked_large_one():
     assert r3["t_admit"] < r2["t_admit"]                 # passed the waiting large one
     assert r3["t_done"] < r1["t_done"]
     assert r2["t_admit"] >= r1["t_done"] - 1e-3          # one large batch at a time
+    s.close()
+
+
+def test_large_requests_merge_when_queued_together():
+    # large requests of one class that wait together run as one batch (up
+    # to merge_large queries); a large request of another class does not
+    # join, nor does one that would pass the limit
+    s = _server(slots=1, budget_bytes=1 << 30, host_bytes=1 << 28, sim_ns_per_query=50,
+                merge_queries=0, small_queries=1000, merge_large=50_000)
+    big = np.zeros((20_000, 3), np.float32)
+    t = [s.submit(0, abx.REQ_NEAREST, big, k=4) for _ in range(3)]
+    other = s.submit(0, abx.REQ_NEAREST, big, k=5)
+    rs = [s.wait(x) for x in t] + [s.wait(other)]
+    assert all(r["status"] == abx.OK for r in rs)
+    st = s.stats()
+    # the first request runs alone (the scheduler admits it at once) or with
+    # the second; the k = 5 request always alone: at most 3 batches of k = 4
+    assert st["completed"] == 4 and st["batches"] <= 3
+    # two requests of 20 000 share a batch: one admission for both
+    admits = sorted(rs[i]["t_admit"] for i in range(3))
+    assert admits[0] == admits[1] or admits[1] == admits[2]
     s.close()
 
 
