@@ -525,10 +525,12 @@ abx_status abx_server_add_tree(abx_server *srv, const abx_bvh *tree, int32_t *id
  * the result of a request whose reservation can never fit: at admission, one
  * larger than an arena; at the fill, one whose result space does not fit
  * while nothing else holds either arena.  A fill that waits for host space
- * held by results not yet released waits for abx_server_release.  Merged
- * requests can complete before requests submitted ahead of them, so a caller
- * whose host arena cannot hold the results in flight must release results in
- * the order they complete (poll), not wait for them in submission order. */
+ * held by results not yet released waits for abx_server_release.  Requests
+ * can complete before requests submitted ahead of them (batches run on
+ * several slots at once, and merged requests finish with their batch), so a
+ * caller whose host arena cannot hold the results in flight must release
+ * results in the order they complete (poll), not wait for them in submission
+ * order. */
 abx_status abx_server_submit(abx_server *srv, const abx_request *req, uint64_t *ticket /*host*/);
 /* ABX_PENDING until the request has completed (results host-visible). */
 abx_status abx_server_poll(abx_server *srv, uint64_t ticket, abx_result *out /*host*/);

@@ -65,20 +65,27 @@ def test_request_larger_than_budget_fails_alone():
 
 def test_radius_two_phases_and_host_release_backpressure():
     # host arena holds only a few results: later requests wait until the
-    # caller releases earlier ones
+    # caller releases earlier ones.  With four slots requests can complete
+    # out of submission order, and a fill may wait for space held by a
+    # later request's results, so the caller releases in completion order
+    # (waiting in submission order could wait on itself)
     s = _server(slots=4, budget_bytes=1 << 30, host_bytes=64 * 1024, sim_ns_per_query=100)
     q = np.zeros((200, 3), np.float32)
     tickets = [s.submit(0, abx.REQ_RADIUS, q, radius=0.1) for _ in range(20)]
-    done = []
-    for t in tickets:
-        r = s.wait(t)
-        assert r["status"] == abx.OK and r["total"] == 10 * 200
-        # count and fill phases; a count that was sent back to the queue (its fill
-        # waited on the others' host space) ran once more
-        phases = r["t_device"] / (200 * 100e-9)
-        assert phases == pytest.approx(round(phases)) and round(phases) >= 2
-        done.append(r)
-        s.release(t)
+    live, deadline = set(tickets), abx.server_now() + 60.0
+    while live and abx.server_now() < deadline:
+        for t in list(live):
+            r = s.poll(t)
+            if r is None:
+                continue
+            assert r["status"] == abx.OK and r["total"] == 10 * 200
+            # count and fill phases; a count that was sent back to the queue
+            # (its fill waited on the others' host space) ran once more
+            phases = r["t_device"] / (200 * 100e-9)
+            assert phases == pytest.approx(round(phases)) and round(phases) >= 2
+            s.release(t)
+            live.discard(t)
+    assert not live, s.stats()
     assert s.stats()["host_high_water"] <= 64 * 1024
     s.close()
 

@@ -21,6 +21,7 @@ def test_scheduler_is_race_free_under_tsan(tmp_path):
     # halt at the first report; the interpreter itself is not instrumented
     env["TSAN_OPTIONS"] = "halt_on_error=1 exitcode=66 report_signal_unsafe=0"
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
+                        "--timeout", "120", "--timeout-method", "thread",
                         os.path.join(ROOT, "tests", "test_serve_cpu.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     out = r.stdout + r.stderr
