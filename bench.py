@@ -58,6 +58,30 @@ def parse():
     return ap.parse_args()
 
 
+def measured_record(kernel, workload, nodes, k):
+    """The committed rocprofv3 counter record of this launch (None when there
+    is none or the kernel sources changed since it was taken)."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        with open(path) as f:
+            rec = json.load(f)
+        if (rec.get("kernel"), rec.get("workload"), rec.get("nodes"), rec.get("k")) != \
+                (kernel, workload, nodes, k):
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        return rec if h.hexdigest() == rec["sources_sha256"] else None
+    return None
+
+
+# VALU issue of the chip: a wave64 instruction holds a 16-lane SIMD for four
+# cycles; 256 CUs x 4 SIMDs at 2.4 GHz
+VALU_PEAK_GINST_S = 256 * 4 * 2.4 / 4
+
+
 def measured_traffic(kernel, workload, nodes, k):
     """HBM bytes per launch from the committed rocprofv3 counter summary:
     (copy-calibrated FETCH_SIZE x 2.0 + WRITE_SIZE, raw FETCH_SIZE + WRITE_SIZE,
@@ -276,6 +300,15 @@ def main():
                         traffic_raw / (ktimes[dom]["ms_per_launch"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     bytes_per_launch=per_launch,
                     ms_per_launch=round(ktimes[dom]["ms_per_launch"], 4))
+        rec = measured_record(dom, args.workload, args.nodes, k)
+        if rec and "valu_insts_per_launch" in rec:
+            # the same launch against the chip's VALU issue rate: the walk is
+            # bound by instruction issue as much as by memory
+            insts = sum(rec["valu_insts_per_launch"].values())
+            gi = insts / (ktimes[dom]["ms_per_launch"] * 1e-3) / 1e9
+            roof["issue"] = dict(valu_insts_per_launch=insts, achieved=round(gi, 1),
+                                 peak=VALU_PEAK_GINST_S, unit="G wave64 VALU instructions/s",
+                                 frac=round(gi / VALU_PEAK_GINST_S, 4))
     else:
         roof = dict(kernel=dom, bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=None, traffic=None)

@@ -77,6 +77,10 @@ def test_committed_traffic_records():
         assert abs(traffic - 1024 * kib) <= 1
         if raw is not None:
             assert abs(raw - 1024 * (fetch + write)) <= 1
+        # the record the issue figure comes from is the same one
+        assert bench.measured_record("nearest+coop", "C3", nodes, 10) == rec
+        if "valu_insts_per_launch" in rec:
+            assert all(v > 0 for v in rec["valu_insts_per_launch"].values())
     assert bench.measured_traffic("nearest+coop", "C3", "q16", 11) == (None, None, None)
 
 
