@@ -582,7 +582,11 @@ int64_t fit_groups(int64_t n) { return (n + kFitGroupLeaves - 1) / kFitGroupLeav
 // the top list: nodes crossing a group boundary, likewise
 uint32_t fit_top_cap(int64_t n) { return (uint32_t)(2 * kFitMaxPath * fit_groups(n) + 64); }
 
-// every node finished by phases 2 and 3 was listed by phase 1 or 2 first
+// Nodes finished by phases 2 and 3: no more than the entries the lists can
+// hold.  Among the nodes whose range crosses a chunk, one with a single
+// crossing child takes one entry and one with none takes two; one whose two
+// children both cross takes none, but in the binary forest they form there
+// are fewer of those than of nodes with no crossing child.
 uint32_t fit_emit_cap(int64_t n) {
   return fit_top_cap(n) + (uint32_t)fit_groups(n) * kFitGroupCap;
 }
