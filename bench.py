@@ -537,9 +537,16 @@ def bench_forest(args):
                   + 32 * int(st[:, 1].astype(np.int64).sum()))
     pair_ms = ktimes.get("forest_nearest", 0.0) + ktimes.get("forest_nearest_coop", 0.0)
     achieved = alg / (pair_ms * 1e-3) / 1e9 if pair_ms > 0 else None
+    rec = measured_record("forest_nearest+coop", "C4", args.nodes, k)
+    traffic = int(rec["traffic_bytes_per_launch"]) if rec else None
+    traffic_raw = int(rec["traffic_bytes_per_launch_raw"]) if rec else None
     roof = {"kernel": "forest_nearest+coop", "bound": "hbm",
             "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": traffic,
+            "traffic_raw": traffic_raw,
+            "traffic_frac": round(traffic / (pair_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            if traffic and pair_ms > 0 else None,
+            "traffic_source": "profiles/traffic_forest_c4_q16.json" if rec else None,
             "bytes_per_launch": alg, "ms_per_launch": round(pair_ms, 4),
             "visits_per_query": round(float(st[:, 0].mean()), 1)}
     cpu = None if args.no_cpu_baseline else forest_cpu_baseline(pts_np, off, q_np, qoff, k, args.cpu_seconds)
