@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per load level of the serving block (0: skip it)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
+    ap.add_argument("--serve-rates", default="700,1400",
+                    help="fixed offered request rates (requests/s), comparable across server versions")
     ap.add_argument("--serve-slots", type=int, default=4, help="server streams (C5)")
     ap.add_argument("--serve-merge", type=int, default=0,
                     help="queries per merged launch (0: the library default, <0: no merging)")
@@ -677,16 +679,23 @@ def bench_serving(args, standalone):
     sat_rps = nreq / span
     out = {"saturated_requests_per_s": round(sat_rps, 1), "saturated_queries_per_s": round(qsum / span, 1),
            "loads": []}
+    def level(seed, rate):
+        lat, gpu_t, qsum, span = run(make(nreq, seed, rate), abx.server_now() + 0.01, paced=True)
+        return {"requests_per_s": round(nreq / span, 1), "queries_per_s": round(qsum / span, 1),
+                "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                # the requests' own GPU time (copies + kernels, stream events)
+                "device_p50_ms": round(1e3 * float(np.percentile(gpu_t, 50)), 3),
+                "device_p99_ms": round(1e3 * float(np.percentile(gpu_t, 99)), 3)}
+
+    # loads relative to this server's saturated rate, then fixed request rates
+    # (the same traffic whatever the server's capacity)
     for i, f in enumerate(float(x) for x in args.serve_loads.split(",")):
-        reqs = make(nreq, 710 + i, f * sat_rps)
-        lat, gpu_t, qsum, span = run(reqs, abx.server_now() + 0.01, paced=True)
-        out["loads"].append({"offered": f, "requests_per_s": round(nreq / span, 1),
-                             "queries_per_s": round(qsum / span, 1),
-                             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
-                             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
-                             # the requests' own GPU time (copies + kernels, stream events)
-                             "device_p50_ms": round(1e3 * float(np.percentile(gpu_t, 50)), 3),
-                             "device_p99_ms": round(1e3 * float(np.percentile(gpu_t, 99)), 3)})
+        out["loads"].append({"offered": f, **level(710 + i, f * sat_rps)})
+    out["fixed_rates"] = []
+    for i, r in enumerate(float(x) for x in args.serve_rates.split(",") if x):
+        if r < sat_rps:
+            out["fixed_rates"].append({"offered_requests_per_s": r, **level(730 + i, r)})
     st = srv.stats()
     out["server"] = {"slots": args.serve_slots, "merge_queries": args.serve_merge,
                      "small_queries": args.serve_small, "merge_large": args.serve_merge_large,

@@ -474,10 +474,10 @@ typedef struct {
   int32_t simulate;
   double sim_ns_per_query;
   int64_t merge_queries;  /* a merged launch holds at most this many queries
-                             (0: 32768; < 0: no merging)                     */
+                             (0: 65536; < 0: no merging)                     */
   int64_t small_queries;  /* requests of at most this many queries are
                              "small", and the two size classes may pass
-                             each other (0: 8192)                           */
+                             each other (0: 16384)                          */
   int64_t merge_large;    /* large requests of one class queued together are
                              merged up to this many queries (0: 4 x
                              merge_queries; < 0: not merged)                */

@@ -757,8 +757,8 @@ abx_status abx_server_create(const abx_server_config *cfg, abx_server **out) {
   abx_server *S = new (std::nothrow) abx_server;
   if (!S) return ABX_ERR_INVALID_ARG;
   S->cfg = *cfg;
-  S->merge_queries = cfg->merge_queries == 0 ? 32768 : std::max<int64_t>(0, cfg->merge_queries);
-  S->small_queries = cfg->small_queries > 0 ? cfg->small_queries : 8192;
+  S->merge_queries = cfg->merge_queries == 0 ? 65536 : std::max<int64_t>(0, cfg->merge_queries);
+  S->small_queries = cfg->small_queries > 0 ? cfg->small_queries : 16384;
   S->merge_large = cfg->merge_large == 0 ? 4 * S->merge_queries : std::max<int64_t>(0, cfg->merge_large);
   S->dev.reset(cfg->arena_bytes);
   S->host.reset(cfg->host_bytes);
