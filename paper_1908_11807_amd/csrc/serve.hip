@@ -759,7 +759,8 @@ abx_status abx_server_create(const abx_server_config *cfg, abx_server **out) {
   S->cfg = *cfg;
   S->merge_queries = cfg->merge_queries == 0 ? 65536 : std::max<int64_t>(0, cfg->merge_queries);
   S->small_queries = cfg->small_queries > 0 ? cfg->small_queries : 16384;
-  S->merge_large = cfg->merge_large == 0 ? 4 * S->merge_queries : std::max<int64_t>(0, cfg->merge_large);
+  S->merge_large = cfg->merge_large == 0 ? 4 * std::min<int64_t>(S->merge_queries, INT64_MAX / 4)
+                                          : std::max<int64_t>(0, cfg->merge_large);
   S->dev.reset(cfg->arena_bytes);
   S->host.reset(cfg->host_bytes);
   S->dev_base = static_cast<char *>(cfg->arena);
