@@ -336,6 +336,15 @@ abx_status abx_radix_sort_check(const void *scratch, int64_t n, int32_t key_bits
                                 abx_stream_t stream);
 int64_t abx_set_sort_spin_limit(int64_t polls);
 
+/* abx_set_refit_table_probes: the refit's passes above its 2048-leaf chunks
+ * (section 2.1, internal node boxes) climb in an LDS table of 2048 nodes; a
+ * pass gives up on the table after this many probes for one node (default
+ * and maximum 2048, the whole table; < 0 restores it) and climbs through
+ * global memory instead.  0 sends every pass to global memory, so tests can
+ * compare the two climbs; the tree is the same either way.  Process-wide;
+ * returns the previous value. */
+int64_t abx_set_refit_table_probes(int64_t probes);
+
 /* -- batched forest --------------------------------------------------------------
  * T independent point sets ("trees", 1 <= T <= 512) of uneven sizes, built
  * and queried together: the batched mode of section 2.2 applied across trees

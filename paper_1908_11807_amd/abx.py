@@ -191,6 +191,8 @@ def _lib():
         L.abx_set_nearest_budget.restype = C.c_int64
         L.abx_set_sort_spin_limit.argtypes = [C.c_int64]
         L.abx_set_sort_spin_limit.restype = C.c_int64
+        L.abx_set_refit_table_probes.argtypes = [C.c_int64]
+        L.abx_set_refit_table_probes.restype = C.c_int64
         L.abx_timing_enable.argtypes = [C.c_int]
         L.abx_timing_enable.restype = None
         L.abx_timing_reset.restype = None
@@ -504,6 +506,13 @@ def set_sort_spin_limit(polls):
     (< 0 restores the default; 0 forces the give-up, for tests).  Returns the
     previous value."""
     return int(_lib().abx_set_sort_spin_limit(int(polls)))
+
+
+def set_refit_table_probes(probes):
+    """Probes of the refit's LDS table per node before a pass climbs through
+    global memory instead (< 0 restores the default, 0 always uses global
+    memory; the tree is the same).  Returns the previous value."""
+    return int(_lib().abx_set_refit_table_probes(int(probes)))
 
 
 class ForestPlan:

@@ -57,6 +57,7 @@ int max_tree_depth();
 // cooperative pass (abx_set_nearest_budget)
 std::atomic<int64_t> g_nearest_budget{22528};
 extern std::atomic<uint32_t> g_sort_spin_limit;  // sort.hip
+extern std::atomic<uint32_t> g_fit_table_probes;  // build.hip
 int64_t nearest_budget() { return g_nearest_budget.load(std::memory_order_relaxed); }
 
 namespace {
@@ -807,6 +808,11 @@ abx_status abx_radix_sort_check(const void *scratch, int64_t n, int32_t key_bits
 int64_t abx_set_sort_spin_limit(int64_t polls) {
   const uint32_t v = polls < 0 ? (1u << 26) : (uint32_t)std::min<int64_t>(polls, UINT32_MAX);
   return g_sort_spin_limit.exchange(v);
+}
+
+int64_t abx_set_refit_table_probes(int64_t probes) {
+  const uint32_t v = probes < 0 ? 2048u : (uint32_t)std::min<int64_t>(probes, 2048);
+  return g_fit_table_probes.exchange(v);
 }
 
 }  // extern "C"

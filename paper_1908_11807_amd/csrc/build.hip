@@ -8,6 +8,7 @@
 //   quantise   -> 16-bit node boxes rounded outward (bandwidth reduction the
 //                 paper cites from the literature; not the paper's own step)
 #include <algorithm>
+#include <atomic>
 
 #include "abx_internal.h"
 
@@ -789,14 +790,15 @@ __global__ __launch_bounds__(kFitThreads) __attribute__((amdgpu_waves_per_eu(kFi
     uint64_t w = pw[r];
     int h = 0;
     for (int step = 0; step < kFitMaxSteps; ++step) {
-      const int32_t pp = (int32_t)(uint32_t)w;
-      const int32_t parent = pp >> 1, j = (int32_t)(uint32_t)(w >> 32);
-      const int side = pp & 1;
+      // parent << 1 | side in the low word (unsigned: parents reach 2^31 - 2)
+      const uint32_t pp = (uint32_t)w;
+      const int32_t parent = (int32_t)(pp >> 1), j = (int32_t)(uint32_t)(w >> 32);
+      const int side = (int)(pp & 1u);
       const int u = parent - c0;
       // the parent's range [min(parent, j), max(parent, j)] inside the chunk
       if ((uint32_t)u >= (uint32_t)kFitChunk || (uint32_t)(j - c0) >= (uint32_t)kFitChunk) {
         put_rec(stage + parent, side, bb, rf, h);
-        fit_push(lists, parent < j ? parent : j, parent < j ? j : parent, pp, hdr);
+        fit_push(lists, parent < j ? parent : j, parent < j ? j : parent, (int32_t)pp, hdr);
         break;
       }
       const int mine = 2 * u + side, other = mine ^ 1;
@@ -849,22 +851,54 @@ __global__ __launch_bounds__(kFitThreads) __attribute__((amdgpu_waves_per_eu(kFi
 }
 
 // Phases 2 and 3: climbs from listed (node, side) entries whose records are
-// staged, counting arrivals in the global flags (cleared by the hierarchy
-// kernel).  kGroup: stop at nodes leaving group blockIdx.x and list them for
+// staged.  kGroup: stop at nodes leaving group blockIdx.x and list them for
 // the top pass.
+//
+// The climbs first run in LDS: the nodes they reach (a group's nodes whose
+// range crosses one of its inner chunk edges, and the first node above the
+// group on each path that leaves it) go into an open-addressing table keyed
+// by node index that holds a node's arrival count and both child records, and
+// arrivals are counted by LDS atomics at workgroup scope.  A step then waits
+// on no global memory but the node's parent word and output slot (read-only),
+// where the climb through global memory also waits for its record store, its
+// arrival atomic and its sibling's record.  Nothing but the header's height
+// is written to global memory until every climb of the workgroup has ended;
+// the finished nodes and the exits are then written from the table.  A group
+// whose nodes do not fit the table (1 520 top-pass nodes and at most 886 per
+// group for 1e7 shell points; a pathological tree can reach
+// 2 x 63 x 96 per group) climbs through global memory instead, from the same
+// untouched lists and records.
+constexpr int kFitHashLog2 = 11;
+constexpr int kFitHash = 1 << kFitHashLog2;
+constexpr uint32_t kFitExit = 1u << 30;  // table count of a node above the group (| side)
+
+// probes of the table per node before a pass gives up on it
+// (abx_set_refit_table_probes; 0 sends every pass through global memory)
+std::atomic<uint32_t> g_fit_table_probes{kFitHash};
+
+// slot of node x in the table (inserted if absent), -1 after `probes`
+// occupied slots (the whole table by default)
+__device__ __forceinline__ int fit_table_slot(int32_t *h_key, int32_t x, uint32_t probes) {
+  const uint32_t h0 = ((uint32_t)x * 2654435761u) >> (32 - kFitHashLog2);
+  for (uint32_t i = 0; i < probes; ++i) {
+    const int s = (int)((h0 + (uint32_t)i) & (kFitHash - 1));
+    const int32_t k = atomicCAS(&h_key[s], -1, x);
+    if (k == -1 || k == x) return s;
+  }
+  return -1;
+}
+
+// the climbs of one workgroup through global memory (counters in `flags`,
+// cleared by the hierarchy kernel; records in the staging nodes)
 template <bool kQ16, bool kGroup>
-__global__ __launch_bounds__(kFitThreads) void k_fit_climb(
-    int64_t n, const uint64_t *__restrict__ pw_int, const int32_t *__restrict__ pre,
-    NodeF32 *stage, uint32_t *flags, TreeHeader *hdr, FitLists lists) {
+__device__ void fit_climb_global(int64_t n, const uint64_t *__restrict__ pw_int,
+                                 const int32_t *__restrict__ pre, NodeF32 *stage, uint32_t *flags,
+                                 TreeHeader *hdr, const FitLists &lists, const int32_t *list,
+                                 uint32_t cnt, int64_t g0, int64_t g1) {
   const int64_t ni = n - 1;
-  const int64_t g0 = kGroup ? (int64_t)blockIdx.x * kFitGroupLeaves : 0;
-  const int64_t g1 = g0 + kFitGroupLeaves;
-  const int32_t *list = kGroup ? lists.group + (int64_t)blockIdx.x * kFitGroupCap : lists.top;
-  const uint32_t cnt =
-      min(lists.count[kGroup ? 1 + blockIdx.x : 0], kGroup ? kFitGroupCap : lists.top_cap);
   for (uint32_t e = threadIdx.x; e < cnt; e += kFitThreads) {
     int32_t pp = list[e];
-    int64_t parent = pp >> 1;
+    int64_t parent = (int64_t)((uint32_t)pp >> 1);
     int side = pp & 1;
     float b[6];
     int32_t ref;
@@ -895,7 +929,7 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_climb(
         break;
       }
       pp = (int32_t)(uint32_t)up;
-      parent = pp >> 1;
+      parent = (int64_t)((uint32_t)pp >> 1);
       side = pp & 1;
       put_rec(stage + parent, side, b, ref, h);
       if (kGroup) {
@@ -909,6 +943,131 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_climb(
         }
       }
       if (step + 1 == kFitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+}
+
+template <bool kQ16, bool kGroup>
+__global__ __launch_bounds__(kFitThreads) void k_fit_climb(
+    int64_t n, const uint64_t *__restrict__ pw_int, const int32_t *__restrict__ pre,
+    NodeF32 *stage, uint32_t *flags, TreeHeader *hdr, FitLists lists, uint32_t probes) {
+  __shared__ int32_t h_key[kFitHash];
+  __shared__ uint32_t h_cnt[kFitHash];
+  __shared__ int32_t h_ref[2 * kFitHash];
+  __shared__ int32_t h_ht[2 * kFitHash];
+  __shared__ float h_box[12 * kFitHash];
+  __shared__ uint32_t s_full;
+  const int64_t ni = n - 1;
+  const int64_t g0 = kGroup ? (int64_t)blockIdx.x * kFitGroupLeaves : 0;
+  const int64_t g1 = g0 + kFitGroupLeaves;
+  const int32_t *list = kGroup ? lists.group + (int64_t)blockIdx.x * kFitGroupCap : lists.top;
+  const uint32_t cnt =
+      min(lists.count[kGroup ? 1 + blockIdx.x : 0], kGroup ? kFitGroupCap : lists.top_cap);
+  // A pass with E entries reaches at most E nodes (every node inside the
+  // group takes two arrivals, entries or climbs from finished nodes, and an
+  // exit one), so up to kFitHash entries always fit; far more than that
+  // seldom do and go to global memory at once.
+  if (cnt > 2u * kFitHash) {
+    fit_climb_global<kQ16, kGroup>(n, pw_int, pre, stage, flags, hdr, lists, list, cnt, g0, g1);
+    return;
+  }
+  for (int i = threadIdx.x; i < kFitHash; i += kFitThreads) {
+    h_key[i] = -1;
+    h_cnt[i] = 0;
+  }
+  if (threadIdx.x == 0) s_full = 0;
+  __syncthreads();
+  for (uint32_t e = threadIdx.x; e < cnt; e += kFitThreads) {
+    const int32_t pp0 = list[e];
+    int32_t x = (int32_t)((uint32_t)pp0 >> 1);
+    int side = pp0 & 1;
+    float b[6];
+    int32_t ref;
+    int h;
+    get_rec(stage + x, side, b, ref, h);
+    for (int step = 0; step < kFitMaxSteps; ++step) {
+      // read-only: fetched ahead of the hand-off
+      const uint64_t up = x != 0 ? pw_int[x] : 0;
+      const int32_t slot = fit_slot(pre, x, ni, hdr);
+      const int sl = fit_table_slot(h_key, x, probes);
+      if (sl < 0) {
+        s_full = 1;
+        break;
+      }
+      const int mine = 2 * sl + side, other = mine ^ 1;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) h_box[6 * mine + a] = b[a];
+      h_ref[mine] = ref;
+      h_ht[mine] = h;
+      const uint32_t old = __hip_atomic_fetch_add(&h_cnt[sl], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], h_box[6 * other + a]);
+        b[3 + a] = fmaxf(b[3 + a], h_box[6 * other + 3 + a]);
+      }
+      const int sh = h_ht[other];
+      h = (h > sh ? h : sh) + 1;
+      ref = slot;
+      if (x == 0) {
+        hdr->height = h;
+        break;
+      }
+      const int32_t pp = (int32_t)(uint32_t)up;
+      x = (int32_t)((uint32_t)pp >> 1);
+      side = pp & 1;
+      if (kGroup) {
+        const int64_t j = (int64_t)(uint32_t)(up >> 32);
+        const int64_t f = x < j ? x : j, l = x < j ? j : x;
+        if (f < g0 || l >= g1) {
+          // the node above the group gets this one arrival from the group
+          // (a node with both children inside the group lies inside it)
+          const int se = fit_table_slot(h_key, x, probes);
+          if (se < 0) {
+            s_full = 1;
+            break;
+          }
+          const int m2 = 2 * se + side;
+#pragma unroll
+          for (int a = 0; a < 6; ++a) h_box[6 * m2 + a] = b[a];
+          h_ref[m2] = ref;
+          h_ht[m2] = h;
+          h_cnt[se] = kFitExit | (uint32_t)side;
+          break;
+        }
+      }
+      if (step + 1 == kFitMaxSteps) atomicOr(&hdr->bad, 4);
+    }
+  }
+  __syncthreads();
+  if (s_full != 0) {
+    fit_climb_global<kQ16, kGroup>(n, pw_int, pre, stage, flags, hdr, lists, list, cnt, g0, g1);
+    return;
+  }
+  // write out: finished nodes whole, exits as staged records listed for the
+  // top pass
+  for (int sl = threadIdx.x; sl < kFitHash; sl += kFitThreads) {
+    const int32_t x = h_key[sl];
+    if (x < 0) continue;
+    const uint32_t c = h_cnt[sl];
+    if (c & kFitExit) {
+      const int side = (int)(c & 1u);
+      put_rec(stage + x, side, &h_box[12 * sl + 6 * side], h_ref[2 * sl + side], h_ht[2 * sl + side]);
+      const uint32_t e2 = atomicAdd(lists.count, 1u);
+      if (e2 < lists.top_cap) lists.top[e2] = (int32_t)(((uint32_t)x << 1) | (uint32_t)side);
+      else atomicOr(&hdr->bad, 4);
+    } else if (c == 2) {
+      put_rec(stage + x, 0, &h_box[12 * sl], h_ref[2 * sl], h_ht[2 * sl]);
+      put_rec(stage + x, 1, &h_box[12 * sl + 6], h_ref[2 * sl + 1], h_ht[2 * sl + 1]);
+      if (kQ16) {
+        const uint32_t e2 = atomicAdd(lists.emit_count, 1u);
+        if (e2 < lists.emit_cap) lists.emit[e2] = x;
+        else atomicOr(&hdr->bad, 4);
+      }
+    } else {
+      // one arrival at a node inside the group: the lists did not form a tree
+      atomicOr(&hdr->bad, 4);
     }
   }
 }
@@ -957,10 +1116,10 @@ __global__ __launch_bounds__(kBuildBlock) void k_pre_init(const uint64_t *__rest
                                                           int64_t ni, uint64_t *__restrict__ w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ni) return;
-  const int32_t pp = i == 0 ? -1 : (int32_t)(uint32_t)pw_int[i];
-  const uint32_t left = pp >= 0 && (pp & 1) == 0 ? 1u : 0u;  // a left child
-  const uint32_t val = pp >= 0 ? left | (1u << 16) : 0u;
-  const int32_t anc = pp >= 0 ? pp >> 1 : -1;
+  const uint32_t pp = i == 0 ? 0u : (uint32_t)pw_int[i];  // parent << 1 | side
+  const uint32_t left = i != 0 && (pp & 1u) == 0 ? 1u : 0u;  // a left child
+  const uint32_t val = i != 0 ? left | (1u << 16) : 0u;
+  const int32_t anc = i != 0 ? (int32_t)(pp >> 1) : -1;
   w[i] = ((uint64_t)val << 32) | (uint32_t)anc;
 }
 
@@ -1251,20 +1410,23 @@ abx_status launch_refit(int kind, bool q16, const float *prims, const int32_t *p
   }
 #undef ABX_FIT
   if (n <= kFitChunk) return ABX_OK;
+  const uint32_t probes = std::min<uint32_t>(g_fit_table_probes.load(std::memory_order_relaxed), kFitHash);
   ABX_TRY(launch("refit_mid", s, [&] {
     if (q16)
       k_fit_climb<true, true><<<(unsigned)groups, kFitThreads, 0, s>>>(n, pw_int, pre, stage, flags,
-                                                                       hdr, L);
+                                                                       hdr, L, probes);
     else
       k_fit_climb<false, true><<<(unsigned)groups, kFitThreads, 0, s>>>(n, pw_int, pre, stage,
-                                                                        flags, hdr, L);
+                                                                        flags, hdr, L, probes);
   }));
   if (n > kFitGroupLeaves)
     ABX_TRY(launch("refit_top", s, [&] {
       if (q16)
-        k_fit_climb<true, false><<<1, kFitThreads, 0, s>>>(n, pw_int, pre, stage, flags, hdr, L);
+        k_fit_climb<true, false><<<1, kFitThreads, 0, s>>>(n, pw_int, pre, stage, flags, hdr, L,
+                                                           probes);
       else
-        k_fit_climb<false, false><<<1, kFitThreads, 0, s>>>(n, pw_int, pre, stage, flags, hdr, L);
+        k_fit_climb<false, false><<<1, kFitThreads, 0, s>>>(n, pw_int, pre, stage, flags, hdr, L,
+                                                            probes);
     }));
   if (!q16) return ABX_OK;
   const unsigned ge = (unsigned)std::min<int64_t>(grid_for(L.emit_cap, kBuildBlock), 1024);

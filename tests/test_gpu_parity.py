@@ -151,6 +151,30 @@ def test_build_group_edges(orc, n, fmt, order):
     _check_tree_vs_oracle(orc, datagen.clusters(n, 90), 0, 21, fmt, order)
 
 
+@pytest.mark.parametrize("n", [2049, 131_073, 300_001, 1_000_000])
+def test_refit_table_and_global_climbs_agree(n):
+    # Above the 2048-leaf chunks the refit climbs in an LDS table; with no
+    # probes every pass climbs through global memory, with one probe some
+    # passes give up on the table midway.  The trees must not differ.
+    pts = datagen.shell(n, 93)
+    got = {}
+    for probes in (-1, 0, 1):
+        prev = abx.set_refit_table_probes(probes)
+        try:
+            for fmt in ("fp32", "q16"):
+                t = abx.bvh_build(dev(pts), node_format=fmt)
+                torch.cuda.synchronize()
+                got[probes, fmt] = (t.height, t.nodes_bytes().cpu(), t.leaves_bytes().cpu())
+                del t
+        finally:
+            abx.set_refit_table_probes(prev)
+    for fmt in ("fp32", "q16"):
+        h, nb, lb = got[-1, fmt]
+        for probes in (0, 1):
+            h2, nb2, lb2 = got[probes, fmt]
+            assert h2 == h and torch.equal(nb2, nb) and torch.equal(lb2, lb), (fmt, probes)
+
+
 def test_build_duplicates_and_degenerate_axis(orc):
     rng = np.random.default_rng(1)
     pts = rng.integers(0, 4, size=(3000, 3)).astype(np.float32)   # heavy duplicates
