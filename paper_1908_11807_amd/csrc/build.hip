@@ -216,6 +216,32 @@ __device__ __forceinline__ int delta(const K *__restrict__ keys, int64_t n, int6
   return (int)(8 * sizeof(K)) + __clz((int)((uint32_t)i ^ (uint32_t)j));
 }
 
+// The same with the keys of positions [lo, hi) staged in LDS (a probe
+// outside the window reads global memory; the value is the same).
+template <typename K>
+struct KeyWindow {
+  const K *keys;
+  const K *lds;
+  int64_t lo, hi;
+  __device__ __forceinline__ K at(int64_t j) const {
+    return j >= lo && j < hi ? lds[j - lo] : keys[j];
+  }
+};
+
+template <typename K>
+__device__ __forceinline__ int delta(const KeyWindow<K> &w, int64_t n, int64_t i, K ki, int64_t j) {
+  if (j < 0 || j >= n) return -1;
+  const K kj = w.at(j);
+  if (ki != kj) return sizeof(K) == 8 ? __clzll((long long)(ki ^ kj)) : __clz((int)(ki ^ kj));
+  return (int)(8 * sizeof(K)) + __clz((int)((uint32_t)i ^ (uint32_t)j));
+}
+
+// A workgroup stages the keys of its nodes and kKarrasHalo positions either
+// side in LDS: most ranges are short, so most searches probe only there; the
+// few long ones leave the window for their outer probes.
+constexpr int kKarrasHalo = 768;
+constexpr int kKarrasWindow = kBuildBlock + 2 * kKarrasHalo;
+
 // One thread per internal node i: direction from the neighbours, range end
 // by exponential then binary search, split by binary search on the prefix,
 // children at gamma / gamma+1 (leaf when the child range has one element).
@@ -230,24 +256,33 @@ __global__ __launch_bounds__(kBuildBlock) void k_karras(const K *__restrict__ ke
                                                         int32_t *__restrict__ other_end,
                                                         uint32_t *__restrict__ flags,
                                                         const TreeHeader *__restrict__ hdr) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ K s_keys[kKarrasWindow];
   // the searches stay inside [i, j] only over sorted keys: after a failed
-  // sort nothing is built (the refit skips as well)
-  if (i >= n - 1 || (hdr->bad & kBadSort)) return;
-  const K ki = keys[i];
-  const int d = delta(keys, n, i, ki, i + 1) - delta(keys, n, i, ki, i - 1) >= 0 ? 1 : -1;
-  const int dmin = delta(keys, n, i, ki, i - d);
+  // sort nothing is built (the refit skips as well); the flag is the same
+  // for the whole workgroup, which leaves before its barrier
+  if (hdr->bad & kBadSort) return;
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t lo = b0 > kKarrasHalo ? b0 - kKarrasHalo : 0;
+  const int64_t hi = b0 + kBuildBlock + kKarrasHalo < n ? b0 + kBuildBlock + kKarrasHalo : n;
+  for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) s_keys[p - lo] = keys[p];
+  __syncthreads();
+  const KeyWindow<K> w{keys, s_keys, lo, hi};
+  const int64_t i = b0 + threadIdx.x;
+  if (i >= n - 1) return;
+  const K ki = w.at(i);
+  const int d = delta(w, n, i, ki, i + 1) - delta(w, n, i, ki, i - 1) >= 0 ? 1 : -1;
+  const int dmin = delta(w, n, i, ki, i - d);
   int64_t lmax = 2;
-  while (delta(keys, n, i, ki, i + lmax * d) > dmin) lmax <<= 1;
+  while (delta(w, n, i, ki, i + lmax * d) > dmin) lmax <<= 1;
   int64_t l = 0;
   for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
-    if (delta(keys, n, i, ki, i + (l + t) * d) > dmin) l += t;
+    if (delta(w, n, i, ki, i + (l + t) * d) > dmin) l += t;
   const int64_t j = i + l * d;
-  const int dnode = delta(keys, n, i, ki, j);
+  const int dnode = delta(w, n, i, ki, j);
   int64_t s = 0, t = l;
   do {
     t = (t + 1) >> 1;
-    if (delta(keys, n, i, ki, i + (s + t) * d) > dnode) s += t;
+    if (delta(w, n, i, ki, i + (s + t) * d) > dnode) s += t;
   } while (t > 1);
   const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
   const int64_t first = i < j ? i : j, last = i < j ? j : i;
