@@ -33,12 +33,20 @@ std::atomic<uint32_t> g_sort_spin_limit{1u << 26};
 namespace {
 
 constexpr int kBlock = 256;                 // 4 waves
-// keys per thread by key width (8 to 24 swept at 1e7: 64-bit keys fastest
-// at 24, i.e. 6144-key tiles; 32-bit keys at 16, i.e. 4096-key tiles)
+// Threads of a onesweep workgroup (the digit work runs on the first kRadix)
+// and keys per thread, by key width.  Swept at 1e7 keys: 64-bit keys, 8
+// passes, 0.866 ms in 256 x 24 (6144-key tiles, two workgroups of 4
+// wavefronts per CU by LDS), 0.74 in 512 x 9, 0.70 in 1024 x 5, 0.692 in
+// 768 x 7 (5376-key tiles, two workgroups of 12 wavefronts); 32-bit keys, 4
+// passes, 0.355 ms in 256 x 16, 0.337 in 512 x 8, 0.333 in 1024 x 5.  More
+// wavefronts per tile shorten each tile's ranking, which a tile's successors
+// wait on, and keep more loads in flight per CU.
 template <typename K>
-constexpr int kItemsOf = sizeof(K) == 8 ? 24 : 16;
+constexpr int kSweepOf = sizeof(K) == 8 ? 768 : 1024;
 template <typename K>
-constexpr int kTileOf = kBlock * kItemsOf<K>;
+constexpr int kItemsOf = sizeof(K) == 8 ? 7 : 5;
+template <typename K>
+constexpr int kTileOf = kSweepOf<K> * kItemsOf<K>;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;     // == kBlock: one digit per thread
@@ -56,8 +64,9 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// exclusive scan of one value per thread over a 256-thread block
-__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *s_tmp /*[kWaves]*/) {
+// exclusive scan of one value per thread over a B-thread block
+template <int B>
+__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *s_tmp /*[B / kWave]*/) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   uint32_t inc = x;
 #pragma unroll
@@ -101,12 +110,12 @@ __global__ __launch_bounds__(kBlock) void k_hist_scan(uint32_t *hist) {
   __shared__ uint32_t s_tmp[kWaves];
   uint32_t *h = hist + blockIdx.x * kRadix;
   const uint32_t x = h[threadIdx.x];
-  const uint32_t e = block_exclusive_scan(x, s_tmp);
+  const uint32_t e = block_exclusive_scan<kBlock>(x, s_tmp);
   h[threadIdx.x] = e;
 }
 
 template <typename K, bool kIota>
-__global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
+__global__ __launch_bounds__(kSweepOf<K>) void k_onesweep(const K *__restrict__ kin,
                                                      const int32_t *__restrict__ vin,
                                                      K *__restrict__ kout, int32_t *__restrict__ vout,
                                                      int64_t n, int shift, int nbits,
@@ -116,10 +125,12 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
                                                      uint32_t *fail_pass, uint32_t *err,
                                                      uint32_t err_bit) {
   constexpr int kItems = kItemsOf<K>, kTile = kTileOf<K>;
-  __shared__ uint32_t s_cnt[kWaves][kRadix];
+  constexpr int kT = kSweepOf<K>, kW = kT / kWave;
+  static_assert(kT >= kRadix && kT % kWave == 0, "a digit per thread among the first kRadix");
+  __shared__ uint32_t s_cnt[kW][kRadix];
   __shared__ uint32_t s_loc[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
-  __shared__ uint32_t s_tmp[kWaves];
+  __shared__ uint32_t s_tmp[kW];
   __shared__ uint32_t s_hist[kRadix];
   __shared__ K s_keys[kTile];
   __shared__ int32_t s_vals[kTile];
@@ -135,8 +146,8 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
     if (f != 0 && f <= (uint32_t)pass) return;
   }
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
-  s_hist[tid] = 0;
+  for (int i = tid; i < kW * kRadix; i += kT) (&s_cnt[0][0])[i] = 0;
+  if (tid < kRadix) s_hist[tid] = 0;
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
@@ -167,9 +178,10 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
   }
   __syncthreads();
   uint32_t *st = status + (size_t)tile * kRadix + tid;
-  const uint32_t total = s_hist[tid];
-  __hip_atomic_store(st, (tile == 0 ? kFlagPre : kFlagAgg) | total, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t total = tid < kRadix ? s_hist[tid] : 0u;
+  if (tid < kRadix)
+    __hip_atomic_store(st, (tile == 0 ? kFlagPre : kFlagAgg) | total, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 
   // Wave ranking: lanes holding the same digit find each other through one
   // ballot per digit bit; the lowest such lane bumps the wave's running
@@ -200,21 +212,21 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
   // per digit (one per thread): exclusive prefix over waves (the sum over
   // the waves is the tile's count, published above)
   const int d = tid;
-  {
+  if (tid < kRadix) {
     uint32_t acc = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < kW; ++w) {
       const uint32_t c = s_cnt[w][d];
       s_cnt[w][d] = acc;
       acc += c;
     }
   }
-  const uint32_t loc = block_exclusive_scan(total, s_tmp);
-  s_loc[d] = loc;
+  const uint32_t loc = block_exclusive_scan<kT>(total, s_tmp);
+  if (tid < kRadix) s_loc[d] = loc;
 
   // decoupled look-back over the preceding tiles for digit d
   uint32_t excl = 0;
-  if (tile != 0) {
+  if (tid < kRadix && tile != 0) {
     int64_t j = (int64_t)tile - 1;
     // Every awaited tile belongs to a resident workgroup, so the wait ends;
     // the spin bound (far above any real wait) only guarantees termination,
@@ -255,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
     }
     __hip_atomic_store(st, kFlagPre | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  s_gbase[d] = digit_start[d] + excl - loc;
+  if (tid < kRadix) s_gbase[d] = digit_start[d] + excl - loc;
   __syncthreads();
 
   // stage in LDS in sorted order
@@ -272,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K *__restrict__ kin,
   __syncthreads();
   const int64_t rem = n - base;
   const int cnt = rem < kTile ? (int)rem : kTile;
-  for (int i = tid; i < cnt; i += kBlock) {
+  for (int i = tid; i < cnt; i += kT) {
     const K kk = s_keys[i];
     const uint32_t dd = (uint32_t)(kk >> shift) & dmask;
     const uint32_t o = s_gbase[dd] + (uint32_t)i;
@@ -381,12 +393,12 @@ abx_status sort_impl(const K *kin, const int32_t *vin, int64_t n, int key_bits, 
     const unsigned g = (unsigned)L.tiles;
     if (p == 0 && src_v == nullptr) {
       ABX_TRY(launch("sort_onesweep", s, [&] {
-        k_onesweep<K, true><<<g, kBlock, 0, s>>>(src_k, nullptr, dk, dv, n, shift, nbits, ds, stp,
+        k_onesweep<K, true><<<g, kSweepOf<K>, 0, s>>>(src_k, nullptr, dk, dv, n, shift, nbits, ds, stp,
                                                  ctr + p, spin_limit, p, fail_pass, err, err_bit);
       }));
     } else {
       ABX_TRY(launch("sort_onesweep", s, [&] {
-        k_onesweep<K, false><<<g, kBlock, 0, s>>>(src_k, src_v, dk, dv, n, shift, nbits, ds, stp,
+        k_onesweep<K, false><<<g, kSweepOf<K>, 0, s>>>(src_k, src_v, dk, dv, n, shift, nbits, ds, stp,
                                                   ctr + p, spin_limit, p, fail_pass, err, err_bit);
       }));
     }

@@ -38,7 +38,7 @@ def test_sort_reports_giveup(forced_giveup, key_bits):
 
 
 def test_single_tile_sort_needs_no_wait(forced_giveup):
-    # one tile (4096 keys of 32 bits) never waits, so it cannot give up
+    # one tile (at most 5120 keys of 32 bits) never waits, so it cannot give up
     keys = np.random.default_rng(3).integers(0, 2 ** 30, size=4096).astype(np.uint32)
     ko, vo = abx.radix_sort_pairs(dev(keys.view(np.int32)), 30)
     assert np.array_equal(vo.cpu().numpy(), np.argsort(keys, kind="stable"))
@@ -75,11 +75,11 @@ def _rows(off, idx):
 
 @pytest.mark.parametrize("fmt", ["fp32", "q16"])
 def test_query_order_falls_back_to_input_order(forced_giveup, fmt):
-    # 6000 points: one tile of 63-bit keys, so the build itself never waits
-    pts = datagen.uniform_cube(6000, 9)
+    # 5000 points: one tile of 63-bit keys (5376 keys), so the build itself never waits
+    pts = datagen.uniform_cube(5000, 9)
     t = abx.bvh_build(dev(pts), node_format=fmt)
-    q = dev(datagen.uniform_cube(20_000, 10))   # five tiles of 30-bit query codes
-    r = float(np.float32(datagen.radius_for_density(6000)))
+    q = dev(datagen.uniform_cube(20_000, 10))   # four tiles of 30-bit query codes (5120 keys)
+    r = float(np.float32(datagen.radius_for_density(5000)))
     print(f"query order give-up, fmt={fmt}", flush=True)
     _, i_s, d_s = abx.query_nearest(t, q, 10, sort_queries=True)
     _, i_u, d_u = abx.query_nearest(t, q, 10, sort_queries=False)

@@ -33,7 +33,10 @@ def test_morton_codes_bit_exact(orc, kind, bits):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 6143, 6144, 6145, 12_289, 100_003])
+# tiles of 5120 32-bit and 5376 64-bit keys: one tile exactly, a key either
+# side, two tiles and a ragged third
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 5119, 5120, 5121, 5375, 5376, 5377, 10_753,
+                               15_361, 100_003])
 @pytest.mark.parametrize("key_bits", [30, 63])
 def test_radix_sort_stable(n, key_bits):
     rng = np.random.default_rng(n + key_bits)
