@@ -301,29 +301,36 @@ struct KnnList {
 // bound of the final one, so nothing the exact walk needs is pruned.
 constexpr int kDeferLanes = 8;
 
+// An empty parking slot.  Parked keys are never negative (a parked distance
+// passed a <= test, so it is a non-negative number, and indices are
+// non-negative), so -1 marks an empty slot; as an inline constant it costs
+// one move to set, where a wider constant can end up reloaded from private
+// memory inside the walk loop.
+constexpr int64_t kPendNone = -1;
+
 struct KnnPending {
   int64_t a, b;
-  __device__ __forceinline__ void init() { a = b = kKeyEmpty; }
+  __device__ __forceinline__ void init() { a = b = kPendNone; }
   template <int K>
   __device__ __forceinline__ void park(KnnList<K> &L, int64_t x) {
-    if (a == kKeyEmpty) a = x;
-    else if (b == kKeyEmpty) b = x;
+    if (a == kPendNone) a = x;
+    else if (b == kPendNone) b = x;
     else L.offer_key(x);
   }
   // called by every active lane of the wavefront
   template <int K>
   __device__ __forceinline__ void flush_some(KnnList<K> &L) {
-    if (__popcll(__ballot(a != kKeyEmpty)) >= kDeferLanes && a != kKeyEmpty) {
+    if (__popcll(__ballot(a != kPendNone)) >= kDeferLanes && a != kPendNone) {
       L.offer_key(a);
       a = b;
-      b = kKeyEmpty;
+      b = kPendNone;
     }
   }
   template <int K>
   __device__ __forceinline__ void flush_all(KnnList<K> &L) {
-    if (a != kKeyEmpty) L.offer_key(a);
-    if (b != kKeyEmpty) L.offer_key(b);
-    a = b = kKeyEmpty;
+    if (a != kPendNone) L.offer_key(a);
+    if (b != kPendNone) L.offer_key(b);
+    a = b = kPendNone;
   }
 };
 
