@@ -299,7 +299,7 @@ struct KnnList {
 // have one waiting (a third candidate goes in at once).  Pruning meanwhile
 // uses the list's k-th distance without the parked candidates: an upper
 // bound of the final one, so nothing the exact walk needs is pruned.
-constexpr int kDeferLanes = 8;
+constexpr int kDeferLanes = 4;
 
 // An empty parking slot.  Parked keys are never negative (a parked distance
 // passed a <= test, so it is a non-negative number, and indices are
