@@ -13,6 +13,9 @@ constexpr int kTravBlock = 256;
 constexpr int kMaxDepth = 128;
 constexpr int kLdsDepthSpatial = 16;
 constexpr int kLdsDepthNearest = 8;
+// the one-lane nearest pass with 16-bit stack distances: 16 six-byte entries
+// per lane still leave six workgroups of 256 lanes per CU
+constexpr int kLdsDepthLane16 = 16;
 constexpr int kMaxRegK = 64;    // largest k kept in registers (lists of 1..64 keys)
 constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 65..128)
 
@@ -200,10 +203,22 @@ __device__ __forceinline__ T stack_pop(ABX_LDS T *lds, const T *ovf, int &sp, in
   return v;
 }
 
-// the nearest traversal's stack holds (node, box distance) pairs
-template <int S, int B>
-__device__ __forceinline__ void stack_push2(ABX_LDS int32_t *ln, ABX_LDS float *ld, int32_t *on,
-                                            float *od, int &sp, int &nl, int32_t n, float d) {
+// The nearest traversal's stack holds (node, box distance) pairs.  The
+// distance is stored as a float, or as its upper 16 bits (DT = uint16_t):
+// truncating a non-negative float rounds it down, so the stored value is a
+// lower bound of the box distance, and a node that the exact value would
+// have pruned when popped is visited instead, its children (boxes inside
+// its box, no nearer) then pruned: the same results, 6-byte entries.
+__device__ __forceinline__ float stk_enc(float d, float) { return d; }
+__device__ __forceinline__ uint16_t stk_enc(float d, uint16_t) {
+  return (uint16_t)(__float_as_uint(d) >> 16);
+}
+__device__ __forceinline__ float stk_dec(float d) { return d; }
+__device__ __forceinline__ float stk_dec(uint16_t d) { return __uint_as_float((uint32_t)d << 16); }
+
+template <int S, int B, typename DT>
+__device__ __forceinline__ void stack_push2(ABX_LDS int32_t *ln, ABX_LDS DT *ld, int32_t *on,
+                                            DT *od, int &sp, int &nl, int32_t n, float d) {
   static_assert((S & (S - 1)) == 0, "window size is a power of two");
   const int slot = (sp & (S - 1)) * B;
   if (nl == S) {
@@ -213,22 +228,22 @@ __device__ __forceinline__ void stack_push2(ABX_LDS int32_t *ln, ABX_LDS float *
     ++nl;
   }
   ln[slot] = n;
-  ld[slot] = d;
+  ld[slot] = stk_enc(d, DT());
   ++sp;
 }
 
-template <int S, int B>
-__device__ __forceinline__ void stack_pop2(ABX_LDS int32_t *ln, ABX_LDS float *ld, const int32_t *on,
-                                           const float *od, int &sp, int &nl, int32_t &n, float &d) {
+template <int S, int B, typename DT>
+__device__ __forceinline__ void stack_pop2(ABX_LDS int32_t *ln, ABX_LDS DT *ld, const int32_t *on,
+                                           const DT *od, int &sp, int &nl, int32_t &n, float &d) {
   --sp;
   if (nl > 0) {
     --nl;
     const int slot = (sp & (S - 1)) * B;
     n = ln[slot];
-    d = ld[slot];
+    d = stk_dec(ld[slot]);
   } else {
     n = on[sp];
-    d = od[sp];
+    d = stk_dec(od[sp]);
   }
 }
 
@@ -361,10 +376,10 @@ __device__ __forceinline__ void knn_leaf(const TreeArgs &t, const KnnQuery &q, i
 // return the nearer qualifying internal child (the farther one is pushed),
 // or -1 when neither qualifies.  `bound` is an external upper bound of the
 // final k-th distance (+inf when there is none).
-template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest, bool DEFER = false>
+template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest, bool DEFER = false, typename DT>
 __device__ __forceinline__ int32_t knn_visit2(const TreeArgs &t, const KnnQuery &q, int32_t node,
                                               float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
-                                              ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
+                                              ABX_LDS DT *lds_d, int32_t *ovf_n, DT *ovf_d,
                                               int &sp, int &nl, int32_t &reads,
                                               KnnPending *pend = nullptr) {
   Kids c;
@@ -457,10 +472,10 @@ __device__ __forceinline__ void wide_slots(const TreeArgs &t, int32_t node, cons
 // the qualifying internal children are visited nearest box centre first:
 // the nearest is returned and the others are pushed farthest first, so they
 // come off the stack in the same order.
-template <int KIND, int K, int B, int S = kLdsDepthNearest, bool DEFER = false>
+template <int KIND, int K, int B, int S = kLdsDepthNearest, bool DEFER = false, typename DT>
 __device__ __forceinline__ int32_t knn_visit_w(const TreeArgs &t, const KnnQuery &q, int32_t node,
                                                float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
-                                               ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
+                                               ABX_LDS DT *lds_d, int32_t *ovf_n, DT *ovf_d,
                                                int &sp, int &nl, int32_t &reads,
                                                KnnPending *pend = nullptr) {
   // each slot is decoded straight into its box distance and centre key, so
@@ -515,10 +530,10 @@ __device__ __forceinline__ int32_t knn_visit_w(const TreeArgs &t, const KnnQuery
   return r[0];
 }
 
-template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest, bool DEFER = false>
+template <int KIND, int FMT, int K, int B, int S = kLdsDepthNearest, bool DEFER = false, typename DT>
 __device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &q, int32_t node,
                                              float bound, KnnList<K> &L, ABX_LDS int32_t *lds_n,
-                                             ABX_LDS float *lds_d, int32_t *ovf_n, float *ovf_d,
+                                             ABX_LDS DT *lds_d, int32_t *ovf_n, DT *ovf_d,
                                              int &sp, int &nl, int32_t &reads,
                                              KnnPending *pend = nullptr) {
   if constexpr (FMT == ABX_NODES_Q16W)
@@ -530,9 +545,9 @@ __device__ __forceinline__ int32_t knn_visit(const TreeArgs &t, const KnnQuery &
 }
 
 // pop deferred nodes until one still qualifies; -1 when the stack runs dry
-template <int B, int S = kLdsDepthNearest>
-__device__ __forceinline__ int32_t knn_pop(float thr, ABX_LDS int32_t *lds_n, ABX_LDS float *lds_d,
-                                           const int32_t *ovf_n, const float *ovf_d, int &sp, int &nl) {
+template <int B, int S = kLdsDepthNearest, typename DT>
+__device__ __forceinline__ int32_t knn_pop(float thr, ABX_LDS int32_t *lds_n, ABX_LDS DT *lds_d,
+                                           const int32_t *ovf_n, const DT *ovf_d, int &sp, int &nl) {
   while (sp > 0) {
     int32_t en;
     float ed;
@@ -589,13 +604,15 @@ static_assert(kHeavyStateWords == 2 + 2 * kHeavyStateEntries + 2 * kMaxRegK, "sa
 // Pass 1 for one query (one lane).  A walk that exceeds `budget` node
 // visits stops and hands the query to the cooperative pass with the k-th
 // distance it has found so far (an upper bound of the final one).
-template <int KIND, int FMT, int K, bool STATS, int B, class Map>
+template <int KIND, int FMT, int K, bool STATS, int B, class Map, typename DT>
 __device__ __forceinline__ void nearest_lane(const TreeArgs &t, const Map &map,
                                              const float *__restrict__ pts, int64_t qi,
-                                             ABX_LDS int32_t *lds_n, ABX_LDS float *lds_d,
+                                             ABX_LDS int32_t *lds_n, ABX_LDS DT *lds_d,
                                              int32_t *__restrict__ indices, float *__restrict__ dist,
                                              int32_t *__restrict__ stats, int64_t budget,
                                              const HeavyList &heavy) {
+  // LDS window entries: 16 with 16-bit distances (6-byte entries), else 8
+  constexpr int kWin = sizeof(DT) == 2 ? kLdsDepthLane16 : kLdsDepthNearest;
   const QInfo info = map.info(qi, t);
   if (info.kk == 0) {
     if (STATS) stats[2 * qi] = stats[2 * qi + 1] = 0;
@@ -612,7 +629,7 @@ __device__ __forceinline__ void nearest_lane(const TreeArgs &t, const Map &map,
     knn_leaf<KIND, FMT, K>(t, q, ~info.root, d, INFINITY, L, reads);
   } else {
     int32_t ovf_n[kMaxDepth];
-    float ovf_d[kMaxDepth];
+    DT ovf_d[kMaxDepth];
     int sp = 0, nl = 0;
     int32_t node = info.root;
     const int64_t limit = budget < t.n ? budget : t.n;
@@ -621,9 +638,9 @@ __device__ __forceinline__ void nearest_lane(const TreeArgs &t, const Map &map,
     done = false;
     for (int64_t it = 0; it < limit; ++it) {
       if (STATS) ++visited;
-      node = knn_visit<KIND, FMT, K, B, kLdsDepthNearest, true>(
+      node = knn_visit<KIND, FMT, K, B, kWin, true>(
           t, q, node, INFINITY, L, lds_n, lds_d, ovf_n, ovf_d, sp, nl, reads, &pend);
-      if (node < 0) node = knn_pop<B>(L.kth(), lds_n, lds_d, ovf_n, ovf_d, sp, nl);
+      if (node < 0) node = knn_pop<B, kWin>(L.kth(), lds_n, lds_d, ovf_n, ovf_d, sp, nl);
       if (node < 0) {
         done = true;
         break;
@@ -649,7 +666,7 @@ __device__ __forceinline__ void nearest_lane(const TreeArgs &t, const Map &map,
           while (sp > 0) {
             int32_t en;
             float ed;
-            stack_pop2<kLdsDepthNearest, B>(lds_n, lds_d, ovf_n, ovf_d, sp, nl, en, ed);
+            stack_pop2<kWin, B>(lds_n, lds_d, ovf_n, ovf_d, sp, nl, en, ed);
             st[2 + 2 * c] = en;
             st[3 + 2 * c] = __float_as_int(ed);
             ++c;
