@@ -277,14 +277,14 @@ __attribute__((amdgpu_waves_per_eu(forest_waves_per_eu(K)))) void k_forest_neare
                                                                  float *__restrict__ dist,
                                                                  int64_t budget, HeavyList heavy,
                                                                  uint32_t *__restrict__ queue, int grab) {
-  __shared__ int32_t s_node[kLdsDepthNearest * kForestBlock];
-  __shared__ float s_dist[kLdsDepthNearest * kForestBlock];
+  __shared__ int32_t s_node[kLdsDepthLane16 * kForestBlock];
+  __shared__ uint16_t s_dist[kLdsDepthLane16 * kForestBlock];
   if (tree_unusable(t)) return;  // abx_forest_check reports why; rows stay unwritten
   resolve_qframe(t);
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t tiles = (M + kWave - 1) / kWave;
   ABX_LDS int32_t *ln = (ABX_LDS int32_t *)(s_node) + threadIdx.x;
-  ABX_LDS float *ld = (ABX_LDS float *)(s_dist) + threadIdx.x;
+  ABX_LDS uint16_t *ld = (ABX_LDS uint16_t *)(s_dist) + threadIdx.x;
   for (int64_t round = 0; round <= tiles; ++round) {
     uint32_t first = 0;
     if (lane == 0) first = atomicAdd(queue, (uint32_t)grab);
@@ -308,14 +308,14 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_nearest_stats(TreeArgs 
                                                                       int64_t M,
                                                                       const int32_t *__restrict__ order,
                                                                       int32_t *__restrict__ stats) {
-  __shared__ int32_t s_node[kLdsDepthNearest * kForestBlock];
-  __shared__ float s_dist[kLdsDepthNearest * kForestBlock];
+  __shared__ int32_t s_node[kLdsDepthLane16 * kForestBlock];
+  __shared__ uint16_t s_dist[kLdsDepthLane16 * kForestBlock];
   if (tree_unusable(t)) return;
   resolve_qframe(t);
   const int64_t tq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tq >= M) return;
   ABX_LDS int32_t *ln = (ABX_LDS int32_t *)(s_node) + threadIdx.x;
-  ABX_LDS float *ld = (ABX_LDS float *)(s_dist) + threadIdx.x;
+  ABX_LDS uint16_t *ld = (ABX_LDS uint16_t *)(s_dist) + threadIdx.x;
   nearest_lane<KIND, FMT, K, true, kForestBlock>(t, map, pts, order[tq], ln, ld, nullptr, nullptr, stats,
                                                  INT64_MAX, HeavyList{});
 }
