@@ -277,8 +277,9 @@ __attribute__((amdgpu_waves_per_eu(forest_waves_per_eu(K)))) void k_forest_neare
                                                                  float *__restrict__ dist,
                                                                  int64_t budget, HeavyList heavy,
                                                                  uint32_t *__restrict__ queue, int grab) {
-  __shared__ int32_t s_node[kLdsDepthLane16 * kForestBlock];
-  __shared__ uint16_t s_dist[kLdsDepthLane16 * kForestBlock];
+  constexpr int W = lane_window(forest_waves_per_eu(K));  // the same window in both forest walks
+  __shared__ int32_t s_node[W * kForestBlock];
+  __shared__ uint16_t s_dist[W * kForestBlock];
   if (tree_unusable(t)) return;  // abx_forest_check reports why; rows stay unwritten
   resolve_qframe(t);
   const int lane = threadIdx.x & (kWave - 1);
@@ -293,7 +294,7 @@ __attribute__((amdgpu_waves_per_eu(forest_waves_per_eu(K)))) void k_forest_neare
     for (int g = 0; g < grab; ++g) {
       const int64_t tq = ((int64_t)first + g) * kWave + lane;
       if (tq < M)
-        nearest_lane<KIND, FMT, K, false, kForestBlock>(t, map, pts, order[tq], ln, ld, indices,
+        nearest_lane<KIND, FMT, K, false, kForestBlock, W>(t, map, pts, order[tq], ln, ld, indices,
                                                         dist, nullptr, budget, heavy);
     }
   }
@@ -308,15 +309,16 @@ __global__ __launch_bounds__(kForestBlock) void k_forest_nearest_stats(TreeArgs 
                                                                       int64_t M,
                                                                       const int32_t *__restrict__ order,
                                                                       int32_t *__restrict__ stats) {
-  __shared__ int32_t s_node[kLdsDepthLane16 * kForestBlock];
-  __shared__ uint16_t s_dist[kLdsDepthLane16 * kForestBlock];
+  constexpr int W = lane_window(forest_waves_per_eu(K));  // the same window in both forest walks
+  __shared__ int32_t s_node[W * kForestBlock];
+  __shared__ uint16_t s_dist[W * kForestBlock];
   if (tree_unusable(t)) return;
   resolve_qframe(t);
   const int64_t tq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tq >= M) return;
   ABX_LDS int32_t *ln = (ABX_LDS int32_t *)(s_node) + threadIdx.x;
   ABX_LDS uint16_t *ld = (ABX_LDS uint16_t *)(s_dist) + threadIdx.x;
-  nearest_lane<KIND, FMT, K, true, kForestBlock>(t, map, pts, order[tq], ln, ld, nullptr, nullptr, stats,
+  nearest_lane<KIND, FMT, K, true, kForestBlock, W>(t, map, pts, order[tq], ln, ld, nullptr, nullptr, stats,
                                                  INT64_MAX, HeavyList{});
 }
 

@@ -160,12 +160,13 @@ __attribute__((amdgpu_waves_per_eu(nearest_waves_per_eu(K, FMT)))) void k_neares
                                                         float *__restrict__ dist,
                                                         int32_t *__restrict__ stats, int64_t budget,
                                                         HeavyList heavy) {
-  __shared__ int32_t s_node[kLdsDepthLane16 * kTravBlock];
-  __shared__ uint16_t s_dist[kLdsDepthLane16 * kTravBlock];
+  constexpr int W = lane_window(nearest_waves_per_eu(K, FMT));
+  __shared__ int32_t s_node[W * kTravBlock];
+  __shared__ uint16_t s_dist[W * kTravBlock];
   const int64_t tq = xcd_tile(blockIdx.x, gridDim.x) * kTravBlock + threadIdx.x;
   if (tq >= m) return;
   const int64_t qi = order ? order[tq] : tq;
-  nearest_lane<KIND, FMT, K, STATS, kTravBlock>(
+  nearest_lane<KIND, FMT, K, STATS, kTravBlock, W>(
       t, map, pts, qi, (ABX_LDS int32_t *)(s_node) + threadIdx.x,
       (ABX_LDS uint16_t *)(s_dist) + threadIdx.x, indices, dist, stats, budget, heavy);
 }

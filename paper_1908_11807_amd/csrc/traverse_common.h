@@ -13,9 +13,11 @@ constexpr int kTravBlock = 256;
 constexpr int kMaxDepth = 128;
 constexpr int kLdsDepthSpatial = 16;
 constexpr int kLdsDepthNearest = 8;
-// the one-lane nearest pass with 16-bit stack distances: 16 six-byte entries
-// per lane still leave six workgroups of 256 lanes per CU
-constexpr int kLdsDepthLane16 = 16;
+// LDS stack window of the one-lane nearest pass (16-bit stack distances,
+// six-byte entries) for an occupancy target of `waves` per SIMD: 16 entries
+// for 256 lanes take 24 KB, which leaves six workgroups per CU; targets
+// above six keep 8 entries (12 KB)
+constexpr int lane_window(int waves) { return waves > 6 ? 8 : 16; }
 constexpr int kMaxRegK = 64;    // largest k kept in registers (lists of 1..64 keys)
 constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 65..128)
 
@@ -604,15 +606,14 @@ static_assert(kHeavyStateWords == 2 + 2 * kHeavyStateEntries + 2 * kMaxRegK, "sa
 // Pass 1 for one query (one lane).  A walk that exceeds `budget` node
 // visits stops and hands the query to the cooperative pass with the k-th
 // distance it has found so far (an upper bound of the final one).
-template <int KIND, int FMT, int K, bool STATS, int B, class Map, typename DT>
+template <int KIND, int FMT, int K, bool STATS, int B, int W, class Map, typename DT>
 __device__ __forceinline__ void nearest_lane(const TreeArgs &t, const Map &map,
                                              const float *__restrict__ pts, int64_t qi,
                                              ABX_LDS int32_t *lds_n, ABX_LDS DT *lds_d,
                                              int32_t *__restrict__ indices, float *__restrict__ dist,
                                              int32_t *__restrict__ stats, int64_t budget,
                                              const HeavyList &heavy) {
-  // LDS window entries: 16 with 16-bit distances (6-byte entries), else 8
-  constexpr int kWin = sizeof(DT) == 2 ? kLdsDepthLane16 : kLdsDepthNearest;
+  constexpr int kWin = W;  // LDS window entries per lane (lds_n, lds_d: stride B)
   const QInfo info = map.info(qi, t);
   if (info.kk == 0) {
     if (STATS) stats[2 * qi] = stats[2 * qi + 1] = 0;
