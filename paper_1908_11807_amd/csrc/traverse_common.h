@@ -17,7 +17,7 @@ constexpr int kLdsDepthNearest = 8;
 // six-byte entries) for an occupancy target of `waves` per SIMD: 16 entries
 // for 256 lanes take 24 KB, which leaves six workgroups per CU; targets
 // above six keep 8 entries (12 KB)
-constexpr int lane_window(int waves) { return waves > 6 ? 8 : 16; }
+constexpr int lane_window(int waves) { return waves > 6 ? 8 : (waves > 3 ? 16 : 32); }
 constexpr int kMaxRegK = 64;    // largest k kept in registers (lists of 1..64 keys)
 constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 65..128)
 
