@@ -14,9 +14,9 @@ constexpr int kMaxDepth = 128;
 constexpr int kLdsDepthSpatial = 16;
 constexpr int kLdsDepthNearest = 8;
 // LDS stack window of the one-lane nearest pass (16-bit stack distances,
-// six-byte entries) for an occupancy target of `waves` per SIMD: 16 entries
-// for 256 lanes take 24 KB, which leaves six workgroups per CU; targets
-// above six keep 8 entries (12 KB)
+// six-byte entries) for an occupancy target of `waves` per SIMD, as large as
+// that many 256-lane workgroups per CU allow: 16 entries take 24 KB (six
+// workgroups), 32 take 48 KB (three); targets above six keep 8 (12 KB)
 constexpr int lane_window(int waves) { return waves > 6 ? 8 : (waves > 3 ? 16 : 32); }
 constexpr int kMaxRegK = 64;    // largest k kept in registers (lists of 1..64 keys)
 constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 65..128)
