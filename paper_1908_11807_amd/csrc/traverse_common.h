@@ -14,10 +14,12 @@ constexpr int kMaxDepth = 128;
 constexpr int kLdsDepthSpatial = 16;
 constexpr int kLdsDepthNearest = 8;
 // LDS stack window of the one-lane nearest pass (16-bit stack distances,
-// six-byte entries) for an occupancy target of `waves` per SIMD, as large as
-// that many 256-lane workgroups per CU allow: 16 entries take 24 KB (six
-// workgroups), 32 take 48 KB (three); targets above six keep 8 (12 KB)
-constexpr int lane_window(int waves) { return waves > 6 ? 8 : (waves > 3 ? 16 : 32); }
+// six-byte entries) for an occupancy target of `waves` per SIMD: 16 entries
+// take 24 KB per 256-lane workgroup (six workgroups per CU), 32 take 48 KB
+// (three).  The 16 entries also cap the k <= 4 walks, whose target is eight
+// waves, at six: at k = 1 on the C3 shell that ran 9 % faster than 8 entries
+// at eight waves.
+constexpr int lane_window(int waves) { return waves > 3 ? 16 : 32; }
 constexpr int kMaxRegK = 64;    // largest k kept in registers (lists of 1..64 keys)
 constexpr int kMaxHeapK = 128;  // largest k (the LDS-heap kernel serves 65..128)
 
